@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of sparse-HRIR rendering on one MI355X.
+
+Workload (the throughput configuration): an HRIR set of 1,250 directions
+(25 azimuths x 50 elevations) x 2 ears x 200 taps, factorized into a 32-tap
+resonance filter and K = 16 kept reflection taps per filter; 64 pink-noise
+sources of 1,048,576 float32 samples, each rendered at 20 distinct
+directions x 2 ears (2,560 output rows of 1,048,775 samples).  One step is
+one render of the whole batch (resonance FIR + sparse gather for every row)
+with inputs resident in HBM.
+
+Prints one JSON line: output samples/s, the HBM roofline of the render
+kernel (algorithmic bytes / measured kernel time vs 8 TB/s), and the FP64
+oracle timed on the host's cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "output samples/s, sparse K=16 vs dense 200-tap on 1 GPU; p99 block latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for fn in ("render.hip",):
+        h.update(open(os.path.join(ROOT, "paper_1502_03162_amd", "csrc", fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    fn = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(fn):
+        return None
+    try:
+        d = json.load(open(fn)).get(name)
+    except (OSError, ValueError):
+        return None
+    if not d or d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_launches(fn, steps: int, warmup: int):
+    """Run fn() warmup times, then time `steps` calls with HIP events on the
+    current stream (the stream the kernels are launched on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(r, srcs, p, g, lg, jobs, n_src_sample: int, chunk: int = 4):
+    """FP64 oracle on the first n_src_sample sources with all their jobs, in
+    chunks of `chunk` sources (bounded host memory); the timed quantity is
+    the oracle's render calls only."""
+    import oracle
+    r64, g64 = r.astype(np.float64), g.astype(np.float64)
+    n_out, dt, n_rows = 0, 0.0, 0
+    for c0 in range(0, n_src_sample, chunk):
+        ids = list(range(c0, min(c0 + chunk, n_src_sample)))
+        sel = [(ids.index(s), f) for (s, f) in jobs if s in ids]
+        ss = [srcs[i].astype(np.float64) for i in ids]
+        lens = [len(x) for x in ss]
+        off = np.concatenate([[0], np.cumsum(lens)[:-1]])
+        cat = np.concatenate(ss)
+        t0 = time.perf_counter()
+        rows = oracle.sparse_render_jobs(r64, cat, off, lens, p, g64, lg, np.asarray(sel, dtype=np.int32))
+        dt += time.perf_counter() - t0
+        n_out += sum(x.size for x in rows)
+        n_rows += len(sel)
+        del rows
+    return {"value": n_out / dt, "unit": "output samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n_src_sample} of the 64 sources with all their {n_rows} (direction, ear) rows "
+                      f"({n_out} outputs), FP64 oracle in chunks of {chunk} sources, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--fact-iters", type=int, default=2000)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--cpu-sources", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    import paper_1502_03162_amd as H
+    import synth
+
+    dev = torch.device("cuda:0")
+    n_src, ns, dps, lf, lg = 64, 1 << 20, 20, 32, 169
+
+    log("HRIR set 1250 directions x 2 ears, factorizing")
+    t0 = time.perf_counter()
+    hs = synth.hrir_set(0, 25, 50)
+    fac = H.factorize(hs.h, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False)
+    e_all = fac["err_db"]
+    energy = np.sum(hs.h ** 2, axis=1)
+    e_agg = float(10 * np.log10(np.sum(10 ** (e_all / 10) * energy) / np.sum(energy)))
+    log(f"factorized in {time.perf_counter() - t0:.1f} s: E_dB aggregate {e_agg:.2f}, worst {e_all.max():.2f}")
+    r = fac["f"].astype(np.float32)
+
+    log("sources: 64 pink x 1,048,576")
+    srcs = [synth.pink(100 + i, ns) for i in range(n_src)]
+    jobs = [(int(a), int(b)) for a, b in synth.jobs_fixed(n_src, 1250, dps)]
+    lens = np.full(n_src, ns, dtype=np.int64)
+    off = (np.arange(n_src) * ns).astype(np.int64)
+
+    plan = H.Plan(r, fac["p"], fac["g"], lg)
+    src = torch.from_numpy(np.concatenate(srcs)).to(dev)
+    out_off, total = H.row_layout(plan, lens, jobs)
+    out = torch.empty(total, dtype=torch.float32, device=dev)
+    flags = H.SPCONV_PERSISTENT if args.persistent else 0
+    batch = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], tile=args.tile,
+                    group=args.group, flags=flags)
+    info = batch.info()
+    n_out = len(jobs) * plan.out_len(ns)
+    log(f"render: {len(jobs)} rows, {n_out} outputs, tiles {info['tiles']} of {info['tile']}, grid {info['grid']}")
+
+    ms, wall = time_launches(lambda: batch.render(src, out), args.steps, args.warmup)
+    value = n_out / (ms * 1e-3)
+    alg_bytes = 4.0 * n_out + 4.0 * n_src * ns       # each output written once, each source read once
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"sparse K={args.k}: {ms:.3f} ms/step, {value:.4g} samples/s, {achieved:.0f} GB/s algorithmic")
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "output samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sparse HRIR render: 64 pink sources x 1,048,576 samples x 20 directions x 2 ears, "
+                               "K=16 of a 169-tap reflection filter, 32-tap resonance, 1,250-direction set",
+                   "sources": n_src, "source_len": ns, "directions_per_source": dps, "ears": 2, "K": args.k,
+                   "lf": lf, "lg": lg, "output_samples": n_out, "tile": info["tile"], "tiles": info["tiles"],
+                   "grid": info["grid"], "persistent": bool(args.persistent)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("render_c1"),
+                     "algorithmic_bytes": alg_bytes, "kernel": "k_render_tiles<32,16>"},
+        "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
+                    "fact_iters": args.fact_iters},
+        "wall_s_timed": wall,
+    }
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log(f"CPU baseline: oracle on {args.cpu_sources} sources")
+        res["cpu_baseline"] = cpu_baseline(r, srcs, fac["p"], fac["g"], lg, jobs, args.cpu_sources)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

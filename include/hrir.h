@@ -1,0 +1,173 @@
+/*
+ * hrir.h -- C ABI of libhrir.so, an MI355X (gfx950) renderer for sparse
+ * head-related impulse responses (Luo, Zotkin, Duraiswami, arXiv 1502.03162).
+ *
+ * The method models every HRIR x as x ~= f * g with one direction-independent
+ * "resonance" filter f and one sparse, non-negative "reflection" filter g per
+ * direction and ear (Sec. II, Eq. (1)).  A source s is then rendered as
+ * (s * f) * g (Eq. (2)): z = f * s once per source, and per (direction, ear)
+ * a K-tap gather  out[t] = sum_k g_k z[t - p_k].
+ *
+ * Conventions for every call:
+ *   - Status: 0 on success, a negative HRIR_E* code on failure.  The message
+ *     of the last failure on the calling thread is hrir_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Every buffer is allocated and owned by the caller unless stated
+ *     otherwise.  "Host" pointers are ordinary CPU memory; "device" pointers
+ *     are HIP device memory of the current device (e.g. a torch tensor's
+ *     data_ptr()).  Opaque handles are owned by the library and released by
+ *     the matching *_destroy call.
+ *   - Matrices are row-major.  A "filter" is one (direction, ear) HRIR; the
+ *     HRIR set is laid out one HRIR per row.
+ *   - Stream arguments are hipStream_t passed as void* (0 = null stream).
+ *     Asynchronous calls return after enqueueing; device buffers must stay
+ *     valid until the stream has reached the work.
+ */
+#ifndef HRIR_H
+#define HRIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HRIR_OK 0
+#define HRIR_EINVAL (-1)   /* bad argument: size, range, null pointer */
+#define HRIR_ENOMEM (-2)   /* host or device allocation failed */
+#define HRIR_ENOTPD (-3)   /* the resonance system of Eq. (11) is not positive definite */
+#define HRIR_EAGAIN (-4)   /* no free slot or memory; retry later (never blocks) */
+#define HRIR_EDEVICE (-5)  /* a HIP runtime call or kernel launch failed */
+
+/* Thread-local message of the last failing call on this thread ("" if none).
+ * The pointer stays valid until the next library call on this thread. */
+const char* hrir_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Factorization: Toeplitz-constrained semi-NMF (Sec. III-C, Alg. 1),
+ * followed by top-K sparsification.  Host only, FP64, synchronous.
+ *
+ * X            host f64[n][m]: the HRIR set, one HRIR per row.
+ * lf           resonance length (the paper's M - K + 1, Eq. (13)); the
+ *              reflection length is lg = m - lf + 1 (so lf + lg - 1 = m).
+ * iters        iterations T of Alg. 1 (>= 1).
+ * seed, g0     initial G: if g0 (host f64[n][lg], entries > 0) is given it
+ *              is used as is, else G0 ~ U(0, 1] from SplitMix64(seed) in
+ *              row-major order (Alg. 1, first step).
+ * lambda0      L1 weight of Eq. (14) applied inside the reflection update:
+ *              lambda0 for the first 10% of the iterations, a geometric decay
+ *              by 10^3 until 50%, 0 for the last half.  0 runs Alg. 1
+ *              unchanged.  f is rescaled to unit norm every iteration
+ *              (the product f * g is unchanged by it).
+ * k            taps kept per reflection filter (1 <= k <= lg): the k largest
+ *              positive entries of each row of G (ties to the lower index),
+ *              stored in ascending position; rows with fewer positive entries
+ *              are padded with (p = 0, g = 0) after their real taps.
+ * flags        HRIR_REFIT_NNLS: replace the kept gains by the non-negative
+ *              least-squares fit of the HRIR on that support with f fixed
+ *              (Eq. (14) with lambda = 0 on the support).
+ * Outputs (host): f_out f64[lf] with ||f||_2 = 1; gdense_out f64[n][lg]
+ * (optional) the dense G scaled to that f; p_out int32[n][k]; g_out
+ * f32[n][k]; nnz_out int32[n] (optional) real taps per row; err_db_out
+ * f64[n] (optional) 10 log10(||x_i - f * ghat_i||^2 / ||x_i||^2) of the
+ * kept taps; cost_out f64[iters] (optional) ||X - F G^T||_F^2 after each
+ * iteration (Eq. (3)).
+ * Errors: EINVAL on sizes out of range or null required pointers; ENOTPD if
+ * the resonance system is singular (e.g. G = 0); ENOMEM.
+ * ---------------------------------------------------------------------- */
+#define HRIR_REFIT_NNLS 1u
+
+int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf, int32_t iters,
+                   uint64_t seed, const double* g0, double lambda0, int32_t k, uint32_t flags,
+                   double* f_out, double* gdense_out, int32_t* p_out, float* g_out,
+                   int32_t* nnz_out, double* err_db_out, double* cost_out);
+
+/* ------------------------------------------------------------------------
+ * Render plan: the resonance filter and the sparse tap table on the device.
+ * (Eq. (2) rendered as (s * f) * g; Sec. IV-F: cost proportional to the
+ * number of kept taps.)
+ *
+ * r            host f32[lf], 1 <= lf <= 64.
+ * p, g         host int32[n_filters][k] positions in [0, lg) and f32 gains
+ *              >= 0 (padding taps may repeat a position with gain 0).
+ * k            1 <= k <= 64.  lg: reflection length, 1 <= lg <= 2048.
+ * The plan copies everything to plan-owned device memory (current device)
+ * and is immutable afterwards: renders on different streams may share it.
+ * Errors: EINVAL (ranges, p outside [0, lg), negative or non-finite g),
+ * ENOMEM, EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct hrir_plan hrir_plan;
+
+int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
+                int32_t k, int32_t lg, hrir_plan** out);
+void spconv_plan_destroy(hrir_plan* plan);
+
+/* One render job: source `src` through filter `filt` into one output row of
+ * length src_len[src] + lf + lg - 2 starting at element out_off of the
+ * output buffer.  Rows of different jobs must not overlap. */
+typedef struct {
+    int32_t src;
+    int32_t filt;
+    int64_t out_off;
+} spconv_job;
+
+/* ------------------------------------------------------------------------
+ * Batch: a fixed job list over a fixed set of sources, prepared once and
+ * rendered many times (the offline path, and the ragged job mix of many
+ * sources, directions and ears in one launch).
+ *
+ * src_off, src_len host int64[n_src]: source i is d_src[src_off[i] ...
+ *              src_off[i] + src_len[i]) of the buffer passed at render time;
+ *              src_len >= 1.
+ * jobs         host spconv_job[n_jobs]; n_jobs may be 0 (render is a no-op).
+ * tile         outputs per work tile: a multiple of 1024 in [1024, 16384]
+ *              (0 = 4096).
+ * group        max jobs sharing one staged z tile (0 = all jobs of a source).
+ * flags        SPCONV_PERSISTENT: one persistent launch over a device tile
+ *              queue instead of one workgroup per tile.
+ *              SPCONV_GRAPH: capture the launch in a HIP graph on first
+ *              render and replay it afterwards (same d_src/d_out required).
+ *              SPCONV_UNFUSED: write z to a batch-owned device buffer with a
+ *              separate resonance kernel, then gather from it (reference
+ *              path for the fused kernel).
+ * The batch owns its device descriptor table (and z buffer when unfused).
+ * Errors: EINVAL (bad indices, lengths, overlapping rows are not checked),
+ * ENOMEM, EDEVICE.
+ * ---------------------------------------------------------------------- */
+#define SPCONV_PERSISTENT 1
+#define SPCONV_GRAPH 2
+#define SPCONV_UNFUSED 4
+
+typedef struct hrir_batch hrir_batch;
+
+int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off, const int64_t* src_len,
+                        int32_t n_src, const spconv_job* jobs, int32_t n_jobs, int32_t tile,
+                        int32_t group, int32_t flags, hrir_batch** out);
+
+/* Enqueue the batch on `stream`: reads d_src (device f32, src_elems
+ * elements), writes every job's output row in d_out (device f32, out_elems
+ * elements).  Asynchronous.  Output elements outside the job rows are not
+ * touched.
+ * Errors: EINVAL (null pointers; a source or job row that does not fit in
+ * the given element counts; SPCONV_GRAPH batch with different buffers than
+ * its first render), EDEVICE. */
+int spconv_batch_render(hrir_batch* batch, const float* d_src, int64_t src_elems, float* d_out,
+                        int64_t out_elems, void* stream);
+
+/* Launch-shape facts of a batch: number of tiles, tile length, jobs per
+ * group, grid size of the launch (host int64[4], written in that order). */
+int spconv_batch_info(const hrir_batch* batch, int64_t* info4);
+void spconv_batch_destroy(hrir_batch* batch);
+
+/* One-shot render: create a batch with default tiling, render it on
+ * `stream`, wait for the stream, destroy the batch.  Synchronous.  Same
+ * arguments and errors as spconv_batch_create + spconv_batch_render. */
+int spconv_render(const hrir_plan* plan, const float* d_src, int64_t src_elems, const int64_t* src_off,
+                  const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs,
+                  float* d_out, int64_t out_elems, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRIR_H */

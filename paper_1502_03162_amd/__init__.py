@@ -1,0 +1,227 @@
+"""Sparse-HRIR rendering on MI355X (gfx950): Python binding of libhrir.so.
+
+Every call below marshals arguments into the C ABI declared in
+``include/hrir.h``; all rendering arithmetic runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device
+(PyTorch provides device memory and streams only).  If ``libhrir.so`` has not
+been built, importing this package raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhrir.so")
+
+HRIR_OK, HRIR_EINVAL, HRIR_ENOMEM, HRIR_ENOTPD, HRIR_EAGAIN, HRIR_EDEVICE = 0, -1, -2, -3, -4, -5
+HRIR_REFIT_NNLS = 1
+SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED = 1, 2, 4
+
+_ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOTPD", -4: "EAGAIN", -5: "EDEVICE"}
+
+
+class HrirError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SpconvJob(ctypes.Structure):
+    _fields_ = [("src", c_int32), ("filt", c_int32), ("out_off", c_int64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1502_03162_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P_d, P_f, P_i32, P_i64 = POINTER(c_double), POINTER(c_float), POINTER(c_int32), POINTER(c_int64)
+    sig = {
+        "hrir_last_error": (c_char_p, []),
+        "hrir_factorize": (c_int, [P_d, c_int32, c_int32, c_int32, c_int32, c_uint64, P_d, c_double, c_int32,
+                                   c_uint32, P_d, P_d, P_i32, P_f, P_i32, P_d, P_d]),
+        "spconv_plan": (c_int, [P_f, c_int32, P_i32, P_f, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+        "spconv_plan_destroy": (None, [c_void_p]),
+        "spconv_batch_create": (c_int, [c_void_p, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32, c_int32,
+                                        c_int32, c_int32, POINTER(c_void_p)]),
+        "spconv_batch_render": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
+        "spconv_batch_info": (c_int, [c_void_p, P_i64]),
+        "spconv_batch_destroy": (None, [c_void_p]),
+        "spconv_render": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
+                                  c_void_p, c_int64, c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_destroy", "spconv_batch_create",
+            "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render")
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HRIR_OK:
+        raise HrirError(rc, _lib.hrir_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(POINTER(ct))
+
+
+def _dev_ptr(t, dtype=None) -> int:
+    """Device address of a contiguous torch tensor on a HIP device."""
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _f32(t):
+    import torch
+    return c_void_p(_dev_ptr(t, torch.float32)), t.numel()
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------------------
+# Factorization (host, FP64)
+# ---------------------------------------------------------------------------
+def factorize(X, lf: int, iters: int, k: int, seed: int = 0, g0=None, lambda0: float = 0.0,
+              refit: bool = True, want_cost: bool = True) -> dict:
+    """Toeplitz-constrained semi-NMF of an HRIR set X [n][m] (Alg. 1) and
+    top-k sparsification.  Returns f, G (dense), p, g, nnz, err_db, cost."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, m = X.shape
+    lg = max(m - lf + 1, 1)
+    f = np.empty(max(lf, 1))
+    G = np.empty((n, lg))
+    p = np.empty((n, max(k, 1)), dtype=np.int32)
+    g = np.empty((n, max(k, 1)), dtype=np.float32)
+    nnz = np.empty(n, dtype=np.int32)
+    err = np.empty(n)
+    cost = np.empty(iters) if want_cost else None
+    g0a = None if g0 is None else np.ascontiguousarray(g0, dtype=np.float64)
+    _check(_lib.hrir_factorize(_ptr(X, c_double), n, m, lf, iters, c_uint64(seed),
+                               None if g0a is None else _ptr(g0a, c_double), lambda0, k,
+                               HRIR_REFIT_NNLS if refit else 0, _ptr(f, c_double), _ptr(G, c_double),
+                               _ptr(p, c_int32), _ptr(g, c_float), _ptr(nnz, c_int32), _ptr(err, c_double),
+                               None if cost is None else _ptr(cost, c_double)))
+    return {"f": f, "G": G, "p": p, "g": g, "nnz": nnz, "err_db": err, "cost": cost}
+
+
+# ---------------------------------------------------------------------------
+# Rendering
+# ---------------------------------------------------------------------------
+class Plan:
+    """Resonance filter r and tap table (p, g) resident on the device."""
+
+    def __init__(self, r, p, g, lg: int):
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        p = np.ascontiguousarray(p, dtype=np.int32)
+        g = np.ascontiguousarray(g, dtype=np.float32)
+        if p.ndim != 2 or p.shape != g.shape:
+            raise ValueError("p and g must be [n_filters][k] arrays of the same shape")
+        self.lf, self.lg = int(r.size), int(lg)
+        self.n_filters, self.k = p.shape
+        h = c_void_p()
+        _check(_lib.spconv_plan(_ptr(r, c_float), r.size, _ptr(p, c_int32), _ptr(g, c_float), p.shape[0],
+                                p.shape[1], lg, byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def out_len(self, src_len: int) -> int:
+        return int(src_len) + self.lf + self.lg - 2
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.spconv_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def make_jobs(rows):
+    """rows: iterable of (src, filt, out_off) -> (ctypes array, count)."""
+    rows = list(rows)
+    arr = (SpconvJob * max(len(rows), 1))()
+    for i, (s, f, o) in enumerate(rows):
+        arr[i].src, arr[i].filt, arr[i].out_off = int(s), int(f), int(o)
+    return arr, len(rows)
+
+
+def row_layout(plan: Plan, src_len, jobs_sf, align: int = 64):
+    """Output offsets for jobs given as (src, filt) pairs: each row starts on
+    an `align`-element boundary.  Returns (out_off int64[n_jobs], total)."""
+    src_len = np.asarray(src_len, dtype=np.int64)
+    off = np.zeros(len(jobs_sf), dtype=np.int64)
+    pos = 0
+    for i, (s, _f) in enumerate(jobs_sf):
+        off[i] = pos
+        pos += (plan.out_len(src_len[s]) + align - 1) // align * align
+    return off, int(pos)
+
+
+class Batch:
+    """A prepared job list over a fixed set of sources (spconv_batch_*)."""
+
+    def __init__(self, plan: Plan, src_off, src_len, jobs, tile: int = 0, group: int = 0, flags: int = 0):
+        self.plan = plan
+        self.src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+        self.src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+        jobs, n_jobs = make_jobs(jobs)
+        self._jobs = jobs
+        self.n_jobs = n_jobs
+        h = c_void_p()
+        _check(_lib.spconv_batch_create(plan.handle, _ptr(self.src_off, c_int64), _ptr(self.src_len, c_int64),
+                                        self.src_len.size, jobs, n_jobs, tile, group, flags, byref(h)))
+        self._h = h
+
+    def info(self) -> dict:
+        a = np.zeros(4, dtype=np.int64)
+        _check(_lib.spconv_batch_info(self._h, _ptr(a, c_int64)))
+        return {"tiles": int(a[0]), "tile": int(a[1]), "group": int(a[2]), "grid": int(a[3])}
+
+    def render(self, src, out, stream=None):
+        """Enqueue on `stream` (default: torch's current stream)."""
+        sp, sn = _f32(src)
+        op, on = _f32(out)
+        _check(_lib.spconv_batch_render(self._h, sp, sn, op, on, c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.spconv_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def render(plan: Plan, src, src_off, src_len, jobs, out, stream=None):
+    """One-shot synchronous render (spconv_render)."""
+    src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+    src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+    jobs, n = make_jobs(jobs)
+    sp, sn = _f32(src)
+    op, on = _f32(out)
+    _check(_lib.spconv_render(plan.handle, sp, sn, _ptr(src_off, c_int64), _ptr(src_len, c_int64), src_len.size,
+                              jobs, n, op, on, c_void_p(_stream_handle(stream))))

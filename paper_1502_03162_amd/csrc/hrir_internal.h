@@ -1,0 +1,44 @@
+// Internal declarations shared by the host and device translation units of
+// libhrir.so (error reporting, plan layout, a small thread pool helper).
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <thread>
+#include <vector>
+#include <algorithm>
+
+#include "hrir.h"
+
+namespace hrir {
+
+// Sets the thread-local last-error message and returns `code`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+const char* last_error();
+
+// Runs body(i) for i in [0, n) on up to hardware_concurrency threads with
+// static contiguous chunks.  Results must not depend on the thread count:
+// callers write disjoint outputs and reduce sequentially afterwards.
+template <class F>
+void parallel_for(int64_t n, F&& body) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::min<int64_t>(hw ? hw : 1, 32);
+    if (n < 64 || nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) body(i);
+        return;
+    }
+    nt = std::min<int64_t>(nt, n);
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        th.emplace_back([b, e, &body] {
+            for (int64_t i = b; i < e; ++i) body(i);
+        });
+    }
+    for (auto& x : th) x.join();
+}
+
+}  // namespace hrir

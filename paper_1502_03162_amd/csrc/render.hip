@@ -1,0 +1,625 @@
+// Sparse-HRIR rendering on gfx950 (CDNA4, wave64).
+//
+// The method renders a source s through the HRIR of one direction and ear as
+// (s * f) * g (Eq. (2)): z = f * s is direction independent and is formed
+// once per source; each (direction, ear) is then a K-tap gather
+//     out[t] = sum_k g_k z[t - p_k],   t in [0, len(s) + lf + lg - 2),
+// whose cost is proportional to the number of kept taps (Sec. IV-F).
+//
+// Work unit ("tile"): one source, TB consecutive output samples, and a group
+// of that source's jobs.  A 256-thread workgroup
+//   1. stages s[t0 - (lg-1) - (lf-1), t0 + TB) in LDS (zero outside the
+//      signal),
+//   2. forms z[t0 - (lg-1), t0 + TB) in LDS with the resonance FIR (each
+//      thread keeps an 8-output sliding window of s in registers; the filter
+//      taps are wave-uniform and live in scalar registers),
+//   3. renders every job of the group from that z tile: each wave takes
+//      (job, 1024-sample chunk) pairs; a job's taps are wave-uniform scalar
+//      loads; lane l accumulates 16 outputs t = c0 + l + 64 j in registers
+//      over the K taps (z read from LDS), then stores them coalesced.
+// z never goes to HBM, and each z tile is shared by all directions and ears
+// of its source: the HBM traffic is one read of s plus one write per output.
+//
+// Summation order per output is fixed (FIR taps 0..lf-1, then kept taps
+// 0..K-1, each a single fma into one accumulator), so every launch shape and
+// batching of the same job gives bitwise identical results.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "hrir_internal.h"
+
+namespace hrir {
+
+constexpr int kThreads = 256;   // 4 wave64 per workgroup
+constexpr int kWaves = kThreads / 64;
+constexpr int kR = 16;          // outputs per lane per chunk
+constexpr int kChunk = 64 * kR; // outputs per wave per chunk
+constexpr int kZpt = 8;         // z values per thread per FIR pass
+constexpr int kMinWaves = 4;    // waves per SIMD the render kernels must fit (<= 128 VGPRs)
+
+struct TileDesc {               // 32 bytes
+    int64_t src_off;            // element offset of the source in d_src
+    int32_t src_len;
+    int32_t out_len;            // src_len + lf + lg - 2
+    int32_t t0;                 // first output sample of the tile
+    int32_t job_begin;          // into the job table (jobs sorted by source)
+    int32_t job_count;
+    int32_t pad;
+};
+
+struct JobDesc {                // 16 bytes
+    int64_t out_off;
+    int32_t filt;
+    int32_t pad;
+};
+
+struct ZDesc {                  // unfused path: one chunk of z of one source
+    int64_t src_off;
+    int64_t z_off;
+    int32_t src_len;
+    int32_t v0;
+};
+
+struct GDesc {                  // unfused path: one chunk of one job
+    int64_t out_off;
+    int64_t z_off;
+    int32_t out_len;
+    int32_t nz;
+    int32_t t0;
+    int32_t filt;
+};
+
+__host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Empty asm that takes 16 accumulators as read-write VGPR operands and
+// clobbers memory: values are materialised here, and memory operations are
+// not moved across it.  It emits no instruction.
+__device__ __forceinline__ void pin16(float (&a)[16]) {
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
+                      "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]),
+                      "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+                 :
+                 : "memory");
+}
+
+// LDS floats needed by one tile: s window then z window.
+__host__ __device__ inline int lds_s_len(int TB, int lg, int lfp) { return round_up(TB + lg - 1, kZpt) + lfp + 4; }
+__host__ __device__ inline int lds_z_len(int TB, int lg) { return round_up(TB + lg - 1, kZpt); }
+
+// ---------------------------------------------------------------------------
+// Tile body: stage s, resonance FIR into LDS, sparse gather from LDS.
+// ---------------------------------------------------------------------------
+template <int LFP, int KP>
+__device__ __forceinline__ void render_tile(const TileDesc& td, const float* __restrict__ src,
+                                            const JobDesc* __restrict__ jobs,
+                                            const float* __restrict__ r, const int* __restrict__ P,
+                                            const float* __restrict__ Gv, float* __restrict__ out,
+                                            int lg, int TB, float* s_win, float* z_win) {
+    const int tid = threadIdx.x;
+    const int H = lg - 1;
+    const int nz8 = lds_z_len(TB, lg);
+    const int ns = lds_s_len(TB, lg, LFP);
+
+    // 1. stage s[sbase + i], zero outside [0, src_len)
+    const int64_t sbase = (int64_t)td.t0 - H - (LFP - 1);
+    const float* sp = src + td.src_off;
+    for (int i = tid; i < ns; i += kThreads) {
+        const int64_t q = sbase + i;
+        s_win[i] = (q >= 0 && q < td.src_len) ? sp[q] : 0.0f;
+    }
+    __syncthreads();
+
+    // 2. z_win[u] = z[t0 - H + u] = sum_n r[n] s_win[u + LFP - 1 - n]
+    float rr[LFP];
+#pragma unroll
+    for (int n = 0; n < LFP; ++n) rr[n] = r[n];
+    for (int u0 = tid * kZpt; u0 < nz8; u0 += kThreads * kZpt) {
+        float w[LFP + kZpt];
+#pragma unroll
+        for (int i = 0; i < LFP + kZpt; i += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(s_win + u0 + i);
+            w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
+        }
+        float zz[kZpt];
+#pragma unroll
+        for (int a = 0; a < kZpt; ++a) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int n = 0; n < LFP; ++n) acc = fmaf(rr[n], w[a + LFP - 1 - n], acc);
+            zz[a] = acc;
+        }
+        *reinterpret_cast<float4*>(z_win + u0) = make_float4(zz[0], zz[1], zz[2], zz[3]);
+        *reinterpret_cast<float4*>(z_win + u0 + 4) = make_float4(zz[4], zz[5], zz[6], zz[7]);
+    }
+    __syncthreads();
+
+    // 3. gather: (job, chunk) pairs round-robin over the waves
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int tile_len = min(TB, td.out_len - td.t0);
+    const int nchunk = (tile_len + kChunk - 1) / kChunk;
+    const int npairs = td.job_count * nchunk;
+    for (int pi = wave; pi < npairs; pi += kWaves) {
+        const int q = pi / nchunk;
+        const int c = pi - q * nchunk;
+        const JobDesc jd = jobs[td.job_begin + q];
+        const int* pp = P + (int64_t)jd.filt * KP;
+        const float* gg = Gv + (int64_t)jd.filt * KP;
+        int pk[KP];
+        float gk[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) { pk[k] = pp[k]; gk[k] = gg[k]; }
+        float acc[kR];
+#pragma unroll
+        for (int j = 0; j < kR; ++j) acc[j] = 0.0f;
+        const float* zl = z_win + (c * kChunk + lane + H);
+        // Two-stage pipeline: the LDS reads of tap k+1 are in flight while the
+        // fmas of tap k run.  pin() materialises the accumulators and is a
+        // compiler memory barrier, so no tap's reads are hoisted further and
+        // no fmas are deferred (either would exhaust the VGPRs).
+        float zv[2][kR];
+#pragma unroll
+        for (int j = 0; j < kR; ++j) zv[0][j] = zl[64 * j - pk[0]];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k + 1 < KP) {
+#pragma unroll
+                for (int j = 0; j < kR; ++j) zv[(k + 1) & 1][j] = zl[64 * j - pk[k + 1]];
+            }
+#pragma unroll
+            for (int j = 0; j < kR; ++j) acc[j] = fmaf(gk[k], zv[k & 1][j], acc[j]);
+            pin16(acc);
+        }
+        float* o = out + jd.out_off + td.t0 + c * kChunk + lane;
+        const int lim = tile_len - c * kChunk - lane;
+#pragma unroll
+        for (int j = 0; j < kR; ++j)
+            if (64 * j < lim) o[64 * j] = acc[j];
+    }
+}
+
+template <int LFP, int KP>
+__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_tiles(const float* __restrict__ src,
+                                                           const TileDesc* __restrict__ tiles,
+                                                           const JobDesc* __restrict__ jobs,
+                                                           const float* __restrict__ r,
+                                                           const int* __restrict__ P,
+                                                           const float* __restrict__ Gv,
+                                                           float* __restrict__ out, int lg, int TB) {
+    extern __shared__ float4 smem4[];
+    float* s_win = reinterpret_cast<float*>(smem4);
+    float* z_win = s_win + lds_s_len(TB, lg, LFP);
+    const TileDesc td = tiles[blockIdx.x];
+    render_tile<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, s_win, z_win);
+}
+
+// Persistent variant: a fixed grid drains the tile list through a device
+// counter.  ctr[0] hands out tiles, ctr[1] counts finished workgroups; the
+// last workgroup to finish resets both, so the next launch (or graph replay)
+// starts from zero without a memset.
+template <int LFP, int KP>
+__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_persistent(const float* __restrict__ src,
+                                                                const TileDesc* __restrict__ tiles,
+                                                                int n_tiles,
+                                                                const JobDesc* __restrict__ jobs,
+                                                                const float* __restrict__ r,
+                                                                const int* __restrict__ P,
+                                                                const float* __restrict__ Gv,
+                                                                float* __restrict__ out, int lg, int TB,
+                                                                int* __restrict__ ctr) {
+    extern __shared__ float4 smem4[];
+    float* s_win = reinterpret_cast<float*>(smem4);
+    float* z_win = s_win + lds_s_len(TB, lg, LFP);
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int t = s_next;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const TileDesc td = tiles[t];
+        render_tile<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, s_win, z_win);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&ctr[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Unfused reference path: z to HBM, then a gather that reads it from HBM.
+// ---------------------------------------------------------------------------
+constexpr int kZChunk = 4096;
+
+template <int LFP>
+__global__ __launch_bounds__(kThreads) void k_resonance(const float* __restrict__ src,
+                                                        const ZDesc* __restrict__ zd,
+                                                        const float* __restrict__ r, int lf,
+                                                        float* __restrict__ zbuf) {
+    const ZDesc d = zd[blockIdx.x];
+    const int nz = d.src_len + lf - 1;
+    const float* sp = src + d.src_off;
+    for (int v = d.v0 + threadIdx.x; v < min(d.v0 + kZChunk, nz); v += kThreads) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int n = 0; n < LFP; ++n) {
+            const int q = v - n;
+            const float sv = (q >= 0 && q < d.src_len) ? sp[q] : 0.0f;
+            acc = fmaf(r[n], sv, acc);
+        }
+        zbuf[d.z_off + v] = acc;
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_gather(const GDesc* __restrict__ gd,
+                                                     const float* __restrict__ zbuf,
+                                                     const int* __restrict__ P,
+                                                     const float* __restrict__ Gv,
+                                                     float* __restrict__ out) {
+    const GDesc d = gd[blockIdx.x];
+    const int* pp = P + (int64_t)d.filt * KP;
+    const float* gg = Gv + (int64_t)d.filt * KP;
+    const float* z = zbuf + d.z_off;
+    for (int t = d.t0 + threadIdx.x; t < min(d.t0 + kZChunk, d.out_len); t += kThreads) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int u = t - pp[k];
+            const float zv = (u >= 0 && u < d.nz) ? z[u] : 0.0f;
+            acc = fmaf(gg[k], zv, acc);
+        }
+        out[d.out_off + t] = acc;
+    }
+}
+
+}  // namespace hrir
+
+// ===========================================================================
+// Host side: plans, batches, launches.
+// ===========================================================================
+using namespace hrir;
+
+struct hrir_plan {
+    int lf, lfp, k, kp, lg, n_filters, device;
+    float* d_r = nullptr;   // [lfp], zero padded
+    int* d_p = nullptr;     // [n_filters][kp], padded with (0, 0)
+    float* d_g = nullptr;
+};
+
+struct hrir_batch {
+    const hrir_plan* plan = nullptr;
+    int flags = 0, TB = 0, group = 0, grid = 0;
+    int64_t n_tiles = 0, n_jobs = 0;
+    int64_t src_extent = 0, out_extent = 0;   // elements the job list touches
+    size_t lds_bytes = 0;
+    TileDesc* d_tiles = nullptr;
+    JobDesc* d_jobs = nullptr;
+    int* d_ctr = nullptr;
+    // unfused
+    ZDesc* d_z = nullptr;
+    GDesc* d_gd = nullptr;
+    float* d_zbuf = nullptr;
+    int64_t n_z = 0, n_gd = 0;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    const float* g_src = nullptr;
+    float* g_out = nullptr;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? HRIR_ENOMEM : HRIR_EDEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                               \
+    } while (0)
+
+int pad_lf(int lf) { return lf <= 16 ? 16 : (lf <= 32 ? 32 : 64); }
+int pad_k(int k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+template <int LFP, int KP>
+void* tiles_kernel_ptr() { return reinterpret_cast<void*>(&k_render_tiles<LFP, KP>); }
+
+// Launch dispatch over the padded (lf, K) instantiations.
+template <class F>
+int dispatch(int lfp, int kp, F&& f) {
+#define HRIR_CASE(L, K) \
+    if (lfp == L && kp == K) return f(std::integral_constant<int, L>{}, std::integral_constant<int, K>{});
+    HRIR_CASE(16, 4) HRIR_CASE(16, 8) HRIR_CASE(16, 16) HRIR_CASE(16, 32) HRIR_CASE(16, 64)
+    HRIR_CASE(32, 4) HRIR_CASE(32, 8) HRIR_CASE(32, 16) HRIR_CASE(32, 32) HRIR_CASE(32, 64)
+    HRIR_CASE(64, 4) HRIR_CASE(64, 8) HRIR_CASE(64, 16) HRIR_CASE(64, 32) HRIR_CASE(64, 64)
+#undef HRIR_CASE
+    return fail(HRIR_EINVAL, "no kernel for lf pad %d, k pad %d", lfp, kp);
+}
+
+void free_batch(hrir_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_jobs);
+    (void)hipFree(b->d_ctr);
+    (void)hipFree(b->d_z);
+    (void)hipFree(b->d_gd);
+    (void)hipFree(b->d_zbuf);
+    delete b;
+}
+
+int launch(hrir_batch* b, const float* d_src, float* d_out, hipStream_t st) {
+    const hrir_plan* pl = b->plan;
+    if (b->n_jobs == 0) return HRIR_OK;
+    if (b->flags & SPCONV_UNFUSED) {
+        int rc = dispatch(pl->lfp, pl->kp, [&](auto L, auto K) -> int {
+            hipLaunchKernelGGL((k_resonance<decltype(L)::value>), dim3((unsigned)b->n_z), dim3(kThreads), 0, st,
+                               d_src, b->d_z, pl->d_r, pl->lf, b->d_zbuf);
+            hipLaunchKernelGGL((k_gather<decltype(K)::value>), dim3((unsigned)b->n_gd), dim3(kThreads), 0, st,
+                               b->d_gd, b->d_zbuf, pl->d_p, pl->d_g, d_out);
+            return HRIR_OK;
+        });
+        if (rc) return rc;
+    } else if (b->flags & SPCONV_PERSISTENT) {
+        int rc = dispatch(pl->lfp, pl->kp, [&](auto L, auto K) -> int {
+            hipLaunchKernelGGL((k_render_persistent<decltype(L)::value, decltype(K)::value>), dim3(b->grid),
+                               dim3(kThreads), b->lds_bytes, st, d_src, b->d_tiles, (int)b->n_tiles, b->d_jobs,
+                               pl->d_r, pl->d_p, pl->d_g, d_out, pl->lg, b->TB, b->d_ctr);
+            return HRIR_OK;
+        });
+        if (rc) return rc;
+    } else {
+        int rc = dispatch(pl->lfp, pl->kp, [&](auto L, auto K) -> int {
+            hipLaunchKernelGGL((k_render_tiles<decltype(L)::value, decltype(K)::value>), dim3((unsigned)b->n_tiles),
+                               dim3(kThreads), b->lds_bytes, st, d_src, b->d_tiles, b->d_jobs, pl->d_r, pl->d_p,
+                               pl->d_g, d_out, pl->lg, b->TB);
+            return HRIR_OK;
+        });
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGetLastError());
+    return HRIR_OK;
+}
+
+}  // namespace
+
+extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
+                           int32_t k, int32_t lg, hrir_plan** out) {
+    clear_error();
+    if (!r || !p || !g || !out) return fail(HRIR_EINVAL, "spconv_plan: null pointer");
+    *out = nullptr;
+    if (lf < 1 || lf > 64) return fail(HRIR_EINVAL, "spconv_plan: lf=%d outside [1, 64]", lf);
+    if (k < 1 || k > 64) return fail(HRIR_EINVAL, "spconv_plan: k=%d outside [1, 64]", k);
+    if (lg < 1 || lg > 2048) return fail(HRIR_EINVAL, "spconv_plan: lg=%d outside [1, 2048]", lg);
+    if (n_filters < 1) return fail(HRIR_EINVAL, "spconv_plan: n_filters=%d < 1", n_filters);
+    for (int i = 0; i < lf; ++i)
+        if (!std::isfinite(r[i])) return fail(HRIR_EINVAL, "spconv_plan: r[%d] not finite", i);
+    for (int64_t i = 0; i < (int64_t)n_filters * k; ++i) {
+        if (p[i] < 0 || p[i] >= lg)
+            return fail(HRIR_EINVAL, "spconv_plan: p[%lld]=%d outside [0, %d)", (long long)i, p[i], lg);
+        if (!(g[i] >= 0.0f) || !std::isfinite(g[i]))
+            return fail(HRIR_EINVAL, "spconv_plan: g[%lld] must be finite and >= 0", (long long)i);
+    }
+    auto* pl = new (std::nothrow) hrir_plan;
+    if (!pl) return fail(HRIR_ENOMEM, "spconv_plan: out of host memory");
+    pl->lf = lf; pl->lfp = pad_lf(lf); pl->k = k; pl->kp = pad_k(k); pl->lg = lg; pl->n_filters = n_filters;
+    std::vector<float> hr(pl->lfp, 0.0f);
+    std::memcpy(hr.data(), r, sizeof(float) * lf);
+    std::vector<int> hp((size_t)n_filters * pl->kp, 0);
+    std::vector<float> hg((size_t)n_filters * pl->kp, 0.0f);
+    for (int f = 0; f < n_filters; ++f)
+        for (int j = 0; j < k; ++j) {
+            hp[(size_t)f * pl->kp + j] = p[(size_t)f * k + j];
+            hg[(size_t)f * pl->kp + j] = g[(size_t)f * k + j];
+        }
+    auto bail = [&](int code) { (void)hipFree(pl->d_r); (void)hipFree(pl->d_p); (void)hipFree(pl->d_g); delete pl; return code; };
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e == hipSuccess) e = hipMalloc(&pl->d_r, hr.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&pl->d_p, hp.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&pl->d_g, hg.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(pl->d_r, hr.data(), hr.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pl->d_p, hp.data(), hp.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pl->d_g, hg.data(), hg.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? HRIR_ENOMEM : HRIR_EDEVICE, "spconv_plan: %s", hipGetErrorString(e)));
+    *out = pl;
+    return HRIR_OK;
+}
+
+extern "C" void spconv_plan_destroy(hrir_plan* plan) {
+    if (!plan) return;
+    (void)hipFree(plan->d_r);
+    (void)hipFree(plan->d_p);
+    (void)hipFree(plan->d_g);
+    delete plan;
+}
+
+extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off, const int64_t* src_len,
+                                   int32_t n_src, const spconv_job* jobs, int32_t n_jobs, int32_t tile,
+                                   int32_t group, int32_t flags, hrir_batch** out) {
+    clear_error();
+    if (!plan || !out || (n_src > 0 && (!src_off || !src_len)) || (n_jobs > 0 && !jobs))
+        return fail(HRIR_EINVAL, "spconv_batch_create: null pointer");
+    *out = nullptr;
+    if (n_src < 0 || n_jobs < 0) return fail(HRIR_EINVAL, "spconv_batch_create: negative count");
+    if (flags & ~(SPCONV_PERSISTENT | SPCONV_GRAPH | SPCONV_UNFUSED))
+        return fail(HRIR_EINVAL, "spconv_batch_create: unknown flags 0x%x", flags);
+    if ((flags & SPCONV_UNFUSED) && (flags & SPCONV_PERSISTENT))
+        return fail(HRIR_EINVAL, "spconv_batch_create: UNFUSED and PERSISTENT are exclusive");
+    if (tile == 0) tile = 4096;
+    if (tile < kChunk || tile % kChunk || tile > 16384)
+        return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, 16384]", tile,
+                    kChunk, kChunk);
+    if (group < 0) return fail(HRIR_EINVAL, "spconv_batch_create: group < 0");
+    const int lf = plan->lf, lg = plan->lg;
+    for (int i = 0; i < n_src; ++i) {
+        if (src_len[i] < 1 || src_len[i] > (int64_t)INT32_MAX - lf - lg)
+            return fail(HRIR_EINVAL, "spconv_batch_create: src_len[%d]=%lld out of range", i, (long long)src_len[i]);
+        if (src_off[i] < 0) return fail(HRIR_EINVAL, "spconv_batch_create: src_off[%d] < 0", i);
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].src < 0 || jobs[j].src >= n_src)
+            return fail(HRIR_EINVAL, "spconv_batch_create: job %d source %d out of range", j, jobs[j].src);
+        if (jobs[j].filt < 0 || jobs[j].filt >= plan->n_filters)
+            return fail(HRIR_EINVAL, "spconv_batch_create: job %d filter %d out of range", j, jobs[j].filt);
+        if (jobs[j].out_off < 0) return fail(HRIR_EINVAL, "spconv_batch_create: job %d out_off < 0", j);
+    }
+    auto* b = new (std::nothrow) hrir_batch;
+    if (!b) return fail(HRIR_ENOMEM, "spconv_batch_create: out of host memory");
+    b->plan = plan; b->flags = flags; b->TB = tile; b->n_jobs = n_jobs;
+    for (int j = 0; j < n_jobs; ++j) {
+        const int s = jobs[j].src;
+        b->src_extent = std::max(b->src_extent, src_off[s] + src_len[s]);
+        b->out_extent = std::max(b->out_extent, jobs[j].out_off + src_len[s] + lf + lg - 2);
+    }
+    // Jobs grouped by source (stable, so a source's jobs keep their order).
+    std::vector<int> order(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [jobs](int a, int c) { return jobs[a].src < jobs[c].src; });
+    std::vector<JobDesc> hj(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) hj[j] = JobDesc{jobs[order[j]].out_off, jobs[order[j]].filt, 0};
+    std::vector<TileDesc> ht;
+    std::vector<ZDesc> hz;
+    std::vector<GDesc> hg;
+    int64_t zsize = 0;
+    int max_group = 0;
+    for (int j0 = 0; j0 < n_jobs;) {
+        const int s = jobs[order[j0]].src;
+        int j1 = j0;
+        while (j1 < n_jobs && jobs[order[j1]].src == s) ++j1;
+        const int njs = j1 - j0;
+        const int gsz = group > 0 ? std::min(group, njs) : njs;
+        max_group = std::max(max_group, gsz);
+        const int64_t out_len = src_len[s] + lf + lg - 2;
+        for (int g0 = j0; g0 < j1; g0 += gsz)
+            for (int64_t t0 = 0; t0 < out_len; t0 += tile)
+                ht.push_back(TileDesc{src_off[s], (int32_t)src_len[s], (int32_t)out_len, (int32_t)t0, g0,
+                                      std::min(gsz, j1 - g0), 0});
+        if (flags & SPCONV_UNFUSED) {
+            const int64_t nz = src_len[s] + lf - 1;
+            for (int64_t v0 = 0; v0 < nz; v0 += kZChunk)
+                hz.push_back(ZDesc{src_off[s], zsize, (int32_t)src_len[s], (int32_t)v0});
+            for (int j = j0; j < j1; ++j)
+                for (int64_t t0 = 0; t0 < out_len; t0 += kZChunk)
+                    hg.push_back(GDesc{hj[j].out_off, zsize, (int32_t)out_len, (int32_t)nz, (int32_t)t0, hj[j].filt});
+            zsize += round_up((int)std::min<int64_t>(nz, INT32_MAX - 64), 64);
+        }
+        j0 = j1;
+    }
+    b->n_tiles = (int64_t)ht.size();
+    b->group = max_group;
+    b->lds_bytes = sizeof(float) * (size_t)(lds_s_len(tile, lg, plan->lfp) + lds_z_len(tile, lg));
+    b->n_z = (int64_t)hz.size();
+    b->n_gd = (int64_t)hg.size();
+    auto bail = [&](int code) { free_batch(b); return code; };
+    if (b->lds_bytes > 160 * 1024)
+        return bail(fail(HRIR_EINVAL, "spconv_batch_create: tile %d with lg %d needs %zu B of LDS (> 160 KiB)", tile, lg,
+                         b->lds_bytes));
+    if (b->n_tiles > INT32_MAX) return bail(fail(HRIR_EINVAL, "spconv_batch_create: too many tiles"));
+    hipError_t e = hipSuccess;
+    if (n_jobs > 0) {
+        e = hipMalloc(&b->d_tiles, ht.size() * sizeof(TileDesc));
+        if (e == hipSuccess) e = hipMalloc(&b->d_jobs, hj.size() * sizeof(JobDesc));
+        if (e == hipSuccess) e = hipMemcpy(b->d_tiles, ht.data(), ht.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_jobs, hj.data(), hj.size() * sizeof(JobDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&b->d_ctr, 2 * sizeof(int));
+        if (e == hipSuccess) e = hipMemset(b->d_ctr, 0, 2 * sizeof(int));
+        if (e == hipSuccess && (flags & SPCONV_UNFUSED)) {
+            e = hipMalloc(&b->d_z, hz.size() * sizeof(ZDesc));
+            if (e == hipSuccess) e = hipMalloc(&b->d_gd, hg.size() * sizeof(GDesc));
+            if (e == hipSuccess) e = hipMalloc(&b->d_zbuf, (size_t)zsize * sizeof(float));
+            if (e == hipSuccess) e = hipMemcpy(b->d_z, hz.data(), hz.size() * sizeof(ZDesc), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(b->d_gd, hg.data(), hg.size() * sizeof(GDesc), hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? HRIR_ENOMEM : HRIR_EDEVICE, "spconv_batch_create: %s",
+                         hipGetErrorString(e)));
+    // Kernel attributes and the persistent grid size.
+    int rc = dispatch(plan->lfp, plan->kp, [&](auto L, auto K) -> int {
+        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        const void* kt = reinterpret_cast<const void*>(&k_render_tiles<LV, KV>);
+        const void* kpers = reinterpret_cast<const void*>(&k_render_persistent<LV, KV>);
+        HIP_TRY(hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes));
+        HIP_TRY(hipFuncSetAttribute(kpers, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes));
+        if (flags & SPCONV_PERSISTENT) {
+            int per_cu = 0, dev = 0, cus = 0;
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, kThreads, b->lds_bytes));
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            b->grid = (int)std::min<int64_t>(std::max(per_cu, 1) * (int64_t)cus, std::max<int64_t>(b->n_tiles, 1));
+        } else {
+            b->grid = (int)std::max<int64_t>(b->n_tiles, 0);
+        }
+        return HRIR_OK;
+    });
+    if (rc) return bail(rc);
+    *out = b;
+    return HRIR_OK;
+}
+
+extern "C" int spconv_batch_render(hrir_batch* b, const float* d_src, int64_t src_elems, float* d_out,
+                                   int64_t out_elems, void* stream) {
+    clear_error();
+    if (!b) return fail(HRIR_EINVAL, "spconv_batch_render: null batch");
+    if (b->n_jobs == 0) return HRIR_OK;
+    if (!d_src || !d_out) return fail(HRIR_EINVAL, "spconv_batch_render: null device pointer");
+    if (src_elems < b->src_extent || out_elems < b->out_extent)
+        return fail(HRIR_EINVAL, "spconv_batch_render: buffers too small (src %lld < %lld or out %lld < %lld)",
+                    (long long)src_elems, (long long)b->src_extent, (long long)out_elems, (long long)b->out_extent);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(b->flags & SPCONV_GRAPH)) return launch(b, d_src, d_out, st);
+    if (!b->exec) {
+        HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = launch(b, d_src, d_out, b->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(HRIR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->g_src = d_src;
+        b->g_out = d_out;
+    } else if (d_src != b->g_src || d_out != b->g_out) {
+        return fail(HRIR_EINVAL, "spconv_batch_render: graph batch replayed with different buffers");
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    return HRIR_OK;
+}
+
+extern "C" int spconv_batch_info(const hrir_batch* b, int64_t* info4) {
+    clear_error();
+    if (!b || !info4) return fail(HRIR_EINVAL, "spconv_batch_info: null pointer");
+    info4[0] = b->n_tiles;
+    info4[1] = b->TB;
+    info4[2] = b->group;
+    info4[3] = b->grid;
+    return HRIR_OK;
+}
+
+extern "C" void spconv_batch_destroy(hrir_batch* b) { free_batch(b); }
+
+extern "C" int spconv_render(const hrir_plan* plan, const float* d_src, int64_t src_elems, const int64_t* src_off,
+                             const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs,
+                             float* d_out, int64_t out_elems, void* stream) {
+    hrir_batch* b = nullptr;
+    int rc = spconv_batch_create(plan, src_off, src_len, n_src, jobs, n_jobs, 0, 0, 0, &b);
+    if (rc) return rc;
+    rc = spconv_batch_render(b, d_src, src_elems, d_out, out_elems, stream);
+    hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    free_batch(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(HRIR_EDEVICE, "spconv_render: %s", hipGetErrorString(e));
+    return HRIR_OK;
+}

@@ -1,0 +1,114 @@
+"""Host-side checks of libhrir.so that need no GPU: every symbol the header
+declares is exported, the FP64 factorization agrees with the oracle from the
+same G0, and argument errors come back as status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1502_03162_amd as H
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M):
+            if m.group(1) not in ("if", "defined"):
+                names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert "spconv_render" in names and "hrir_factorize" in names
+    lib = ctypes.CDLL(H.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_factorize_matches_oracle_same_g0():
+    hs = synth.hrir_set(2, 2, 5)
+    X = hs.h
+    n, m = X.shape
+    lf, k, T = 32, 16, 60
+    G0 = oracle.rand_g0(9, n, m - lf + 1)
+    lib = H.factorize(X, lf, T, k, g0=G0, lambda0=0.2)
+    f, G, tr = oracle.factorize(X, lf, T, G0, 0.2)
+    assert np.max(np.abs(lib["f"] - f)) < 1e-10
+    assert np.max(np.abs(lib["G"] - G)) < 1e-10 * np.max(G)
+    assert np.max(np.abs(lib["cost"] - tr) / tr) < 1e-10
+    rec_lib = oracle.reconstruct(lib["f"], lib["G"])
+    rec_or = oracle.reconstruct(f, G)
+    assert np.linalg.norm(rec_lib - rec_or) / np.linalg.norm(rec_or) < 1e-8
+    p, g, nnz = oracle.topk(G, k)
+    assert np.array_equal(lib["p"], p) and np.array_equal(lib["nnz"], nnz)
+    gr = oracle.refit(X, f, p, nnz)
+    assert np.max(np.abs(lib["g"] - gr.astype(np.float32))) <= 2e-7 * np.max(gr)
+    # reported error of the kept taps
+    rec = oracle.reconstruct(f, oracle.scatter_taps(p, gr, m - lf + 1))
+    e = np.array([oracle.e_db(X[i], rec[i]) for i in range(n)])
+    assert np.max(np.abs(lib["err_db"] - e)) < 1e-6
+
+
+def test_factorize_raw_gains_without_refit():
+    hs = synth.hrir_set(4, 2, 2)
+    G0 = oracle.rand_g0(1, 8, 169)
+    lib = H.factorize(hs.h, 32, 20, 8, g0=G0, refit=False)
+    p, g, nnz = oracle.topk(lib["G"], 8)
+    assert np.array_equal(lib["p"], p)
+    assert np.array_equal(lib["g"], g.astype(np.float32))
+
+
+def test_factorize_seed_equals_splitmix_g0():
+    hs = synth.hrir_set(5, 1, 3)
+    a = H.factorize(hs.h, 32, 5, 4, seed=123)
+    b = H.factorize(hs.h, 32, 5, 4, g0=oracle.rand_g0(123, 6, 169))
+    assert np.array_equal(a["G"], b["G"]) and np.array_equal(a["f"], b["f"])
+
+
+def test_factorize_errors():
+    X = np.ones((4, 20))
+    with pytest.raises(H.HrirError) as e:
+        H.factorize(X, 25, 3, 2)                     # lf > m
+    assert e.value.code == H.HRIR_EINVAL
+    with pytest.raises(H.HrirError) as e:
+        H.factorize(X, 5, 3, 17)                     # k > lg = 16
+    assert e.value.code == H.HRIR_EINVAL
+    with pytest.raises(H.HrirError) as e:
+        H.factorize(X, 5, 3, 2, g0=np.zeros((4, 16)))  # G0 must be > 0
+    assert e.value.code == H.HRIR_EINVAL
+    with pytest.raises(H.HrirError) as e:
+        H.factorize(np.zeros((4, 20)), 5, 3, 2)      # f vanishes
+    assert e.value.code == H.HRIR_ENOTPD
+    Xn = X.copy(); Xn[1, 3] = np.nan
+    with pytest.raises(H.HrirError) as e:
+        H.factorize(Xn, 5, 3, 2)
+    assert e.value.code == H.HRIR_EINVAL
+    assert "not finite" in str(e.value)
+
+
+def test_plan_argument_errors_before_any_device_call():
+    r = np.ones(4, dtype=np.float32)
+    ok_p = np.zeros((2, 3), dtype=np.int32)
+    ok_g = np.ones((2, 3), dtype=np.float32)
+    for args, msg in [
+        ((r, np.full((2, 3), 9, dtype=np.int32), ok_g, 9), "outside"),       # p >= lg
+        ((r, -ok_p - 1, ok_g, 9), "outside"),                                 # p < 0
+        ((r, ok_p, -ok_g, 9), ">= 0"),                                        # negative gain
+        ((np.ones(65, dtype=np.float32), ok_p, ok_g, 9), "lf=65"),           # lf too long
+        ((r, np.zeros((2, 65), dtype=np.int32), np.zeros((2, 65), dtype=np.float32), 9), "k=65"),
+        ((r, ok_p, ok_g, 0), "lg=0"),
+    ]:
+        with pytest.raises(H.HrirError) as e:
+            H.Plan(*args)
+        assert e.value.code == H.HRIR_EINVAL and msg in str(e.value)
