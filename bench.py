@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--kernel", choices=["quad", "lds_gather", "regwin"], default="quad",
+                    help="fused render kernel (quad: default)")
     ap.add_argument("--cpu-sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -144,12 +146,14 @@ def main():
     src = torch.from_numpy(np.concatenate(srcs)).to(dev)
     out_off, total = H.row_layout(plan, lens, jobs)
     out = torch.empty(total, dtype=torch.float32, device=dev)
-    flags = H.SPCONV_PERSISTENT if args.persistent else 0
+    flags = (H.SPCONV_PERSISTENT if args.persistent else 0) | {"quad": 0, "lds_gather": H.SPCONV_LDS_GATHER,
+                                                                "regwin": H.SPCONV_REGWIN}[args.kernel]
     batch = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], tile=args.tile,
                     group=args.group, flags=flags)
     info = batch.info()
     n_out = len(jobs) * plan.out_len(ns)
-    log(f"render: {len(jobs)} rows, {n_out} outputs, tiles {info['tiles']} of {info['tile']}, grid {info['grid']}")
+    log(f"render ({info['kernel']}): {len(jobs)} rows, {n_out} outputs, tiles {info['tiles']} of {info['tile']}, "
+        f"grid {info['grid']}")
 
     ms, wall = time_launches(lambda: batch.render(src, out), args.steps, args.warmup)
     value = n_out / (ms * 1e-3)
@@ -174,10 +178,12 @@ def main():
                                "K=16 of a 169-tap reflection filter, 32-tap resonance, 1,250-direction set",
                    "sources": n_src, "source_len": ns, "directions_per_source": dps, "ears": 2, "K": args.k,
                    "lf": lf, "lg": lg, "output_samples": n_out, "tile": info["tile"], "tiles": info["tiles"],
-                   "grid": info["grid"], "persistent": bool(args.persistent)},
+                   "grid": info["grid"], "persistent": bool(args.persistent), "kernel": info["kernel"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("render_c1"),
-                     "algorithmic_bytes": alg_bytes, "kernel": "k_render_tiles<32,16>"},
+                     "algorithmic_bytes": alg_bytes,
+                     "kernel": {"quad": "k_render_quad<32,16>", "register_window": "k_render_rw<32>",
+                                "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters},
         "wall_s_timed": wall,

@@ -120,8 +120,10 @@ typedef struct {
  *              src_off[i] + src_len[i]) of the buffer passed at render time;
  *              src_len >= 1.
  * jobs         host spconv_job[n_jobs]; n_jobs may be 0 (render is a no-op).
- * tile         outputs per work tile: a multiple of 1024 in [1024, 16384]
- *              (0 = 4096).
+ * tile         outputs per work tile: a multiple of 1024 up to 4096 for the
+ *              default kernel (default 2048), of 1024 up to 16384 for
+ *              LDS_GATHER (default 4096), of 6144 up to 16384 for REGWIN
+ *              (default 6144).
  * group        max jobs sharing one staged z tile (0 = all jobs of a source).
  * flags        SPCONV_PERSISTENT: one persistent launch over a device tile
  *              queue instead of one workgroup per tile.
@@ -130,6 +132,14 @@ typedef struct {
  *              SPCONV_UNFUSED: write z to a batch-owned device buffer with a
  *              separate resonance kernel, then gather from it (reference
  *              path for the fused kernel).
+ *              SPCONV_LDS_GATHER: fused kernel that reads each tap's z from
+ *              one LDS copy of the z tile, 8 bytes per lane per read.
+ *              SPCONV_REGWIN: fused kernel that keeps each lane's z window
+ *              in registers (needs lg <= 169).
+ *              Default: the fused quad kernel, which keeps 4 shifted copies
+ *              of the z tile in LDS so every tap read is 16 bytes per lane.
+ *              All kernels sum every output in the same order, so results
+ *              are bitwise identical across kernels and launch shapes.
  * The batch owns its device descriptor table (and z buffer when unfused).
  * Errors: EINVAL (bad indices, lengths, overlapping rows are not checked),
  * ENOMEM, EDEVICE.
@@ -137,6 +147,8 @@ typedef struct {
 #define SPCONV_PERSISTENT 1
 #define SPCONV_GRAPH 2
 #define SPCONV_UNFUSED 4
+#define SPCONV_LDS_GATHER 8
+#define SPCONV_REGWIN 16
 
 typedef struct hrir_batch hrir_batch;
 
@@ -154,9 +166,10 @@ int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off, const int
 int spconv_batch_render(hrir_batch* batch, const float* d_src, int64_t src_elems, float* d_out,
                         int64_t out_elems, void* stream);
 
-/* Launch-shape facts of a batch: number of tiles, tile length, jobs per
- * group, grid size of the launch (host int64[4], written in that order). */
-int spconv_batch_info(const hrir_batch* batch, int64_t* info4);
+/* Launch-shape facts of a batch (host int64[5], in this order): number of
+ * tiles, tile length, jobs per group, grid size of the launch, kernel
+ * (0 quad, 1 register window, 2 LDS gather, 3 unfused). */
+int spconv_batch_info(const hrir_batch* batch, int64_t* info5);
 void spconv_batch_destroy(hrir_batch* batch);
 
 /* One-shot render: create a batch with default tiling, render it on

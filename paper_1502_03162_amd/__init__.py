@@ -14,12 +14,17 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_float, c_int, c_int32, 
 
 import numpy as np
 
+# torch first: libhrir.so then binds to the HIP runtime torch already loaded
+# (same soname), so device pointers and streams from torch are valid in it.
+# Loading the library first would bring in a second HIP runtime.
+import torch  # noqa: F401  (load order matters)
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhrir.so")
 
 HRIR_OK, HRIR_EINVAL, HRIR_ENOMEM, HRIR_ENOTPD, HRIR_EAGAIN, HRIR_EDEVICE = 0, -1, -2, -3, -4, -5
 HRIR_REFIT_NNLS = 1
-SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED = 1, 2, 4
+SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED, SPCONV_LDS_GATHER, SPCONV_REGWIN = 1, 2, 4, 8, 16
 
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOTPD", -4: "EAGAIN", -5: "EDEVICE"}
 
@@ -198,9 +203,10 @@ class Batch:
         self._h = h
 
     def info(self) -> dict:
-        a = np.zeros(4, dtype=np.int64)
+        a = np.zeros(5, dtype=np.int64)
         _check(_lib.spconv_batch_info(self._h, _ptr(a, c_int64)))
-        return {"tiles": int(a[0]), "tile": int(a[1]), "group": int(a[2]), "grid": int(a[3])}
+        return {"tiles": int(a[0]), "tile": int(a[1]), "group": int(a[2]), "grid": int(a[3]),
+                "kernel": ("quad", "register_window", "lds_gather", "unfused")[int(a[4])]}
 
     def render(self, src, out, stream=None):
         """Enqueue on `stream` (default: torch's current stream)."""

@@ -13,18 +13,25 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
-SOURCES = ["render.hip", "factorize.cpp", "errors.cpp"]
+SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "factorize.cpp", "errors.cpp"]
+
+# Per-file extra flags.  The register-window kernel dispatches taps through a
+# tree of wave-uniform scalar branches; the structurizer must leave such
+# uniform regions as they are (structurizing them inserts flow blocks whose
+# phis copy the accumulators after every tap).
+EXTRA = {"render_rw.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 VALU ops stay off; plain fp32 fma is what the kernels use
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
+
+_NOISE = "packed-fp32-ops' is not a recognized feature"
 
 
 def hipcc() -> str:
@@ -34,23 +41,32 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [
-        os.path.join(CSRC, s) for s in sorted(os.listdir(CSRC))
-        if s.endswith((".hip", ".cpp")) and s not in SOURCES
-    ]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs,
-           "-lhipfft"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "packed-fp32-ops' is not a recognized feature"
-    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
+    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if _NOISE not in l)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msgs}")
     if verbose and msgs.strip():
         print(msgs)
+
+
+def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src + ".o")
+        jobs.append(([hipcc(), *HIPCC_FLAGS, *EXTRA.get(src, []), *inc, "-c", "-o", obj,
+                      os.path.join(CSRC, src)], obj))
+    with ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    tmp = LIB + ".tmp"
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for _, o in jobs], "-lhipfft"],
+         verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -30,64 +30,9 @@
 #include <mutex>
 
 #include "hrir_internal.h"
+#include "render_common.h"
 
 namespace hrir {
-
-constexpr int kThreads = 256;   // 4 wave64 per workgroup
-constexpr int kWaves = kThreads / 64;
-constexpr int kR = 16;          // outputs per lane per chunk
-constexpr int kChunk = 64 * kR; // outputs per wave per chunk
-constexpr int kZpt = 8;         // z values per thread per FIR pass
-constexpr int kMinWaves = 4;    // waves per SIMD the render kernels must fit (<= 128 VGPRs)
-
-struct TileDesc {               // 32 bytes
-    int64_t src_off;            // element offset of the source in d_src
-    int32_t src_len;
-    int32_t out_len;            // src_len + lf + lg - 2
-    int32_t t0;                 // first output sample of the tile
-    int32_t job_begin;          // into the job table (jobs sorted by source)
-    int32_t job_count;
-    int32_t pad;
-};
-
-struct JobDesc {                // 16 bytes
-    int64_t out_off;
-    int32_t filt;
-    int32_t pad;
-};
-
-struct ZDesc {                  // unfused path: one chunk of z of one source
-    int64_t src_off;
-    int64_t z_off;
-    int32_t src_len;
-    int32_t v0;
-};
-
-struct GDesc {                  // unfused path: one chunk of one job
-    int64_t out_off;
-    int64_t z_off;
-    int32_t out_len;
-    int32_t nz;
-    int32_t t0;
-    int32_t filt;
-};
-
-__host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
-
-// Empty asm that takes 16 accumulators as read-write VGPR operands and
-// clobbers memory: values are materialised here, and memory operations are
-// not moved across it.  It emits no instruction.
-__device__ __forceinline__ void pin16(float (&a)[16]) {
-    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
-                      "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]),
-                      "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
-                 :
-                 : "memory");
-}
-
-// LDS floats needed by one tile: s window then z window.
-__host__ __device__ inline int lds_s_len(int TB, int lg, int lfp) { return round_up(TB + lg - 1, kZpt) + lfp + 4; }
-__host__ __device__ inline int lds_z_len(int TB, int lg) { return round_up(TB + lg - 1, kZpt); }
 
 // ---------------------------------------------------------------------------
 // Tile body: stage s, resonance FIR into LDS, sparse gather from LDS.
@@ -100,41 +45,7 @@ __device__ __forceinline__ void render_tile(const TileDesc& td, const float* __r
                                             int lg, int TB, float* s_win, float* z_win) {
     const int tid = threadIdx.x;
     const int H = lg - 1;
-    const int nz8 = lds_z_len(TB, lg);
-    const int ns = lds_s_len(TB, lg, LFP);
-
-    // 1. stage s[sbase + i], zero outside [0, src_len)
-    const int64_t sbase = (int64_t)td.t0 - H - (LFP - 1);
-    const float* sp = src + td.src_off;
-    for (int i = tid; i < ns; i += kThreads) {
-        const int64_t q = sbase + i;
-        s_win[i] = (q >= 0 && q < td.src_len) ? sp[q] : 0.0f;
-    }
-    __syncthreads();
-
-    // 2. z_win[u] = z[t0 - H + u] = sum_n r[n] s_win[u + LFP - 1 - n]
-    float rr[LFP];
-#pragma unroll
-    for (int n = 0; n < LFP; ++n) rr[n] = r[n];
-    for (int u0 = tid * kZpt; u0 < nz8; u0 += kThreads * kZpt) {
-        float w[LFP + kZpt];
-#pragma unroll
-        for (int i = 0; i < LFP + kZpt; i += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(s_win + u0 + i);
-            w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
-        }
-        float zz[kZpt];
-#pragma unroll
-        for (int a = 0; a < kZpt; ++a) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int n = 0; n < LFP; ++n) acc = fmaf(rr[n], w[a + LFP - 1 - n], acc);
-            zz[a] = acc;
-        }
-        *reinterpret_cast<float4*>(z_win + u0) = make_float4(zz[0], zz[1], zz[2], zz[3]);
-        *reinterpret_cast<float4*>(z_win + u0 + 4) = make_float4(zz[4], zz[5], zz[6], zz[7]);
-    }
-    __syncthreads();
+    stage_z<LFP>(td, src, r, H, TB, s_win, z_win);
 
     // 3. gather: (job, chunk) pairs round-robin over the waves
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -297,6 +208,7 @@ struct hrir_plan {
 struct hrir_batch {
     const hrir_plan* plan = nullptr;
     int flags = 0, TB = 0, group = 0, grid = 0;
+    int kind = 0;                             // KIND_* below
     int64_t n_tiles = 0, n_jobs = 0;
     int64_t src_extent = 0, out_extent = 0;   // elements the job list touches
     size_t lds_bytes = 0;
@@ -317,6 +229,8 @@ struct hrir_batch {
 };
 
 namespace {
+
+enum { KIND_QUAD = 0, KIND_REGWIN = 1, KIND_LDS_GATHER = 2, KIND_UNFUSED = 3 };
 
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
@@ -369,6 +283,16 @@ int launch(hrir_batch* b, const float* d_src, float* d_out, hipStream_t st) {
                                b->d_gd, b->d_zbuf, pl->d_p, pl->d_g, d_out);
             return HRIR_OK;
         });
+        if (rc) return rc;
+    } else if (b->kind == KIND_QUAD) {
+        int rc = quad_launch(pl->lfp, pl->kp, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st, d_src,
+                             b->d_tiles, (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p, pl->d_g, d_out, pl->lg, b->TB,
+                             b->d_ctr);
+        if (rc) return rc;
+    } else if (b->kind == KIND_REGWIN) {
+        int rc = rw_launch(pl->lfp, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st, d_src, b->d_tiles,
+                           (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p, pl->d_g, d_out, pl->kp, pl->k, b->TB,
+                           b->d_ctr);
         if (rc) return rc;
     } else if (b->flags & SPCONV_PERSISTENT) {
         int rc = dispatch(pl->lfp, pl->kp, [&](auto L, auto K) -> int {
@@ -452,14 +376,26 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return fail(HRIR_EINVAL, "spconv_batch_create: null pointer");
     *out = nullptr;
     if (n_src < 0 || n_jobs < 0) return fail(HRIR_EINVAL, "spconv_batch_create: negative count");
-    if (flags & ~(SPCONV_PERSISTENT | SPCONV_GRAPH | SPCONV_UNFUSED))
+    if (flags & ~(SPCONV_PERSISTENT | SPCONV_GRAPH | SPCONV_UNFUSED | SPCONV_LDS_GATHER | SPCONV_REGWIN))
         return fail(HRIR_EINVAL, "spconv_batch_create: unknown flags 0x%x", flags);
+    const int kflags = flags & (SPCONV_UNFUSED | SPCONV_LDS_GATHER | SPCONV_REGWIN);
+    if (kflags & (kflags - 1))
+        return fail(HRIR_EINVAL, "spconv_batch_create: UNFUSED, LDS_GATHER and REGWIN are exclusive");
     if ((flags & SPCONV_UNFUSED) && (flags & SPCONV_PERSISTENT))
         return fail(HRIR_EINVAL, "spconv_batch_create: UNFUSED and PERSISTENT are exclusive");
-    if (tile == 0) tile = 4096;
-    if (tile < kChunk || tile % kChunk || tile > 16384)
-        return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, 16384]", tile,
-                    kChunk, kChunk);
+    if ((flags & SPCONV_REGWIN) && plan->lg > kHW + 1)
+        return fail(HRIR_EINVAL, "spconv_batch_create: the register-window kernel needs lg <= %d (lg=%d)", kHW + 1,
+                    plan->lg);
+    const int kind = (flags & SPCONV_UNFUSED) ? KIND_UNFUSED
+                     : (flags & SPCONV_REGWIN) ? KIND_REGWIN
+                     : (flags & SPCONV_LDS_GATHER) ? KIND_LDS_GATHER
+                                                   : KIND_QUAD;
+    const int tile_unit = kind == KIND_REGWIN ? kTileRW : kChunk;
+    const int tile_max = kind == KIND_QUAD ? kQuadTileMax : 16384;
+    if (tile == 0) tile = kind == KIND_REGWIN ? kTileRW : kind == KIND_QUAD ? 2048 : 4096;
+    if (tile < tile_unit || tile % tile_unit || tile > tile_max)
+        return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, %d]", tile,
+                    tile_unit, tile_unit, tile_max);
     if (group < 0) return fail(HRIR_EINVAL, "spconv_batch_create: group < 0");
     const int lf = plan->lf, lg = plan->lg;
     for (int i = 0; i < n_src; ++i) {
@@ -476,7 +412,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     }
     auto* b = new (std::nothrow) hrir_batch;
     if (!b) return fail(HRIR_ENOMEM, "spconv_batch_create: out of host memory");
-    b->plan = plan; b->flags = flags; b->TB = tile; b->n_jobs = n_jobs;
+    b->plan = plan; b->flags = flags; b->TB = tile; b->n_jobs = n_jobs; b->kind = kind;
     for (int j = 0; j < n_jobs; ++j) {
         const int s = jobs[j].src;
         b->src_extent = std::max(b->src_extent, src_off[s] + src_len[s]);
@@ -518,7 +454,9 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     }
     b->n_tiles = (int64_t)ht.size();
     b->group = max_group;
-    b->lds_bytes = sizeof(float) * (size_t)(lds_s_len(tile, lg, plan->lfp) + lds_z_len(tile, lg));
+    b->lds_bytes = kind == KIND_REGWIN ? (size_t)rw_lds_bytes(tile, plan->lfp)
+                   : kind == KIND_QUAD ? (size_t)quad_lds_bytes(tile, lg, plan->lfp)
+                                       : sizeof(float) * (size_t)(lds_s_len(tile, lg, plan->lfp) + lds_z_len(tile, lg));
     b->n_z = (int64_t)hz.size();
     b->n_gd = (int64_t)hg.size();
     auto bail = [&](int code) { free_batch(b); return code; };
@@ -546,7 +484,11 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return bail(fail(e == hipErrorOutOfMemory ? HRIR_ENOMEM : HRIR_EDEVICE, "spconv_batch_create: %s",
                          hipGetErrorString(e)));
     // Kernel attributes and the persistent grid size.
-    int rc = dispatch(plan->lfp, plan->kp, [&](auto L, auto K) -> int {
+    int rc = kind == KIND_REGWIN ? rw_prepare(plan->lfp, b->lds_bytes, (flags & SPCONV_PERSISTENT) != 0, b->n_tiles,
+                                              &b->grid)
+             : kind == KIND_QUAD ? quad_prepare(plan->lfp, plan->kp, b->lds_bytes, (flags & SPCONV_PERSISTENT) != 0,
+                                                b->n_tiles, &b->grid)
+                                 : dispatch(plan->lfp, plan->kp, [&](auto L, auto K) -> int {
         constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
         const void* kt = reinterpret_cast<const void*>(&k_render_tiles<LV, KV>);
         const void* kpers = reinterpret_cast<const void*>(&k_render_persistent<LV, KV>);
@@ -598,13 +540,14 @@ extern "C" int spconv_batch_render(hrir_batch* b, const float* d_src, int64_t sr
     return HRIR_OK;
 }
 
-extern "C" int spconv_batch_info(const hrir_batch* b, int64_t* info4) {
+extern "C" int spconv_batch_info(const hrir_batch* b, int64_t* info5) {
     clear_error();
-    if (!b || !info4) return fail(HRIR_EINVAL, "spconv_batch_info: null pointer");
-    info4[0] = b->n_tiles;
-    info4[1] = b->TB;
-    info4[2] = b->group;
-    info4[3] = b->grid;
+    if (!b || !info5) return fail(HRIR_EINVAL, "spconv_batch_info: null pointer");
+    info5[0] = b->n_tiles;
+    info5[1] = b->TB;
+    info5[2] = b->group;
+    info5[3] = b->grid;
+    info5[4] = b->kind;
     return HRIR_OK;
 }
 

@@ -1,0 +1,260 @@
+// Quad LDS-gather sparse render kernel for gfx950 (the default render path).
+//
+// Same tiling as the other fused kernels (one source, TB outputs, a group of
+// that source's (direction, ear) jobs per 256-thread workgroup; z formed in
+// LDS by the resonance FIR and shared by every job of the tile), but the z
+// tile is kept as four copies shifted by 0..3 samples:
+//     Zc[m] = z[t0 - H + m + c],   c = 0..3.
+// Lane l of a wave owns outputs q = c0 + 4 l + 256 j + i (i < 4, j < 4) of
+// a 1024-output chunk.  For a tap at position p the four outputs of a quad
+// read z[t0 + q - p + i] = Zc[q + H - p - c + i] with c = (H - p) mod 4,
+// and q + H - p - c is a multiple of 4: one aligned 16-byte LDS read feeds 4
+// fmas, and the lanes of a wave read 1 KiB of consecutive LDS (no bank
+// conflicts).  The quad layout also makes every global store 16 bytes per
+// lane, 1 KiB per wave instruction.
+//
+// The FIR keeps its z values in registers across a barrier, so the copies
+// can overwrite the staged source: LDS per tile is 4 (TB + H) floats.
+//
+// Summation order per output: FIR taps 0..lf-1, then kept taps 0..K-1, one
+// fma each into one accumulator -- the order of every other kernel, so the
+// results are bitwise identical to theirs.
+#include <hip/hip_runtime.h>
+
+#include "hrir_internal.h"
+#include "render_common.h"
+
+namespace hrir {
+
+constexpr int kQR = 16;               // outputs per lane per chunk (4 quads)
+constexpr int kQChunk = 64 * kQR;     // outputs per wave per chunk
+constexpr int kQMaxPass = 4;          // FIR passes of 8 z values per thread
+static_assert(kQChunk == 1024, "quad chunk");
+
+// Floats per shifted copy: holds m < TB + H (+ padding so that the copies
+// start on different banks).
+__host__ __device__ inline int quad_cs(int TB, int H) { return round_up(TB + H + 4, 8) + 4; }
+
+__host__ __device__ inline int lds_quad_len(int TB, int lg, int lfp) {
+    const int H = lg - 1;
+    const int s_len = round_up(TB + H + 3, kZpt) + lfp + 4;
+    const int c_len = 4 * quad_cs(TB, H);
+    return s_len > c_len ? s_len : c_len;
+}
+
+template <int LFP, int KP>
+__device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float* __restrict__ src,
+                                                 const JobDesc* __restrict__ jobs, const float* __restrict__ r,
+                                                 const int* __restrict__ P, const float* __restrict__ Gv,
+                                                 float* __restrict__ out, int lg, int TB, float* lds) {
+    const int tid = threadIdx.x;
+    const int H = lg - 1;
+    const int NZ = TB + H + 3;                 // z_win[u], u < NZ, covers every quad read
+    const int nz8 = round_up(NZ, kZpt);
+    const int CS = quad_cs(TB, H);
+    float* s_win = lds;
+    float* zc = lds;                           // the copies overwrite s_win after the FIR
+
+    stage_s<LFP>(td, src, H, nz8, s_win);
+
+    // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)
+    float rr[LFP];
+#pragma unroll
+    for (int n = 0; n < LFP; ++n) rr[n] = r[n];
+    float zz[kQMaxPass][kZpt];
+#pragma unroll
+    for (int ps = 0; ps < kQMaxPass; ++ps) {
+        const int u0 = (ps * kThreads + tid) * kZpt;
+        if (u0 < nz8) {
+            float w[LFP + kZpt];
+#pragma unroll
+            for (int i = 0; i < LFP + kZpt; i += 4) {
+                const float4 v = *reinterpret_cast<const float4*>(s_win + u0 + i);
+                w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
+            }
+#pragma unroll
+            for (int a = 0; a < kZpt; ++a) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int n = 0; n < LFP; ++n) acc = fmaf(rr[n], w[a + LFP - 1 - n], acc);
+                zz[ps][a] = acc;
+            }
+        }
+    }
+    __syncthreads();                            // every read of s_win is done
+    // Zc[m] = z_win[m + c] for m < TB + H
+    const int mlim = TB + H;
+#pragma unroll
+    for (int ps = 0; ps < kQMaxPass; ++ps) {
+        const int u0 = (ps * kThreads + tid) * kZpt;
+        if (u0 < nz8) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int a = 0; a < kZpt; ++a) {
+                    const int m = u0 + a - c;
+                    if (m >= 0 && m < mlim) zc[c * CS + m] = zz[ps][a];
+                }
+        }
+    }
+    __syncthreads();
+
+    // gather: (job, chunk) pairs round-robin over the waves
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int tile_len = min(TB, td.out_len - td.t0);
+    const int nchunk = (tile_len + kQChunk - 1) / kQChunk;
+    const int npairs = td.job_count * nchunk;
+    for (int pi = wave; pi < npairs; pi += kWaves) {
+        const int q = pi / nchunk;
+        const int ch = pi - q * nchunk;
+        const JobDesc jd = jobs[td.job_begin + q];
+        const int* pp = P + (int64_t)jd.filt * KP;
+        const float* gg = Gv + (int64_t)jd.filt * KP;
+        int pk[KP];
+        float gk[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) { pk[k] = pp[k]; gk[k] = gg[k]; }
+        float acc[kQR];
+#pragma unroll
+        for (int j = 0; j < kQR; ++j) acc[j] = 0.0f;
+        const float* zl = zc + ch * kQChunk + 4 * lane;
+        // Two-stage pipeline as in the other LDS kernel: reads of tap k+1 in
+        // flight during the fmas of tap k; pin16 keeps the compiler from
+        // hoisting every tap's reads.
+        float4 zv[2][4];
+        {
+            const int c = (H - pk[0]) & 3;
+            const float* a = zl + c * CS + (H - pk[0] - c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) zv[0][j] = *reinterpret_cast<const float4*>(a + 256 * j);
+        }
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k + 1 < KP) {
+                const int c = (H - pk[k + 1]) & 3;
+                const float* a = zl + c * CS + (H - pk[k + 1] - c);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) zv[(k + 1) & 1][j] = *reinterpret_cast<const float4*>(a + 256 * j);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 v = zv[k & 1][j];
+                acc[4 * j + 0] = fmaf(gk[k], v.x, acc[4 * j + 0]);
+                acc[4 * j + 1] = fmaf(gk[k], v.y, acc[4 * j + 1]);
+                acc[4 * j + 2] = fmaf(gk[k], v.z, acc[4 * j + 2]);
+                acc[4 * j + 3] = fmaf(gk[k], v.w, acc[4 * j + 3]);
+            }
+            pin16(acc);
+        }
+        float* orow = out + jd.out_off + td.t0 + ch * kQChunk;
+        const int lim = tile_len - ch * kQChunk;    // valid outputs in this chunk (uniform)
+        if (lim >= kQChunk && ((reinterpret_cast<uintptr_t>(orow) & 15) == 0)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                *reinterpret_cast<float4*>(orow + 4 * lane + 256 * j) =
+                    make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qo = 4 * lane + 256 * j + i;
+                    if (qo < lim) orow[qo] = acc[4 * j + i];
+                }
+        }
+    }
+}
+
+template <int LFP, int KP>
+__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_quad(const float* __restrict__ src,
+                                                                     const TileDesc* __restrict__ tiles,
+                                                                     const JobDesc* __restrict__ jobs,
+                                                                     const float* __restrict__ r,
+                                                                     const int* __restrict__ P,
+                                                                     const float* __restrict__ Gv,
+                                                                     float* __restrict__ out, int lg, int TB) {
+    extern __shared__ float4 smem4[];
+    const TileDesc td = tiles[blockIdx.x];
+    render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4));
+}
+
+// Persistent variant over the device tile counter (see k_render_persistent).
+template <int LFP, int KP>
+__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_quad_persistent(
+    const float* __restrict__ src, const TileDesc* __restrict__ tiles, int n_tiles,
+    const JobDesc* __restrict__ jobs, const float* __restrict__ r, const int* __restrict__ P,
+    const float* __restrict__ Gv, float* __restrict__ out, int lg, int TB, int* __restrict__ ctr) {
+    extern __shared__ float4 smem4[];
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int t = s_next;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const TileDesc td = tiles[t];
+        render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4));
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&ctr[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
+        }
+    }
+}
+
+int quad_lds_bytes(int TB, int lg, int lfp) { return (int)sizeof(float) * lds_quad_len(TB, lg, lfp); }
+
+template <class F>
+static int with_lf_k(int lfp, int kp, F&& f) {
+#define HRIR_QCASE(L, K) \
+    if (lfp == L && kp == K) return f(std::integral_constant<int, L>{}, std::integral_constant<int, K>{});
+    HRIR_QCASE(16, 4) HRIR_QCASE(16, 8) HRIR_QCASE(16, 16) HRIR_QCASE(16, 32) HRIR_QCASE(16, 64)
+    HRIR_QCASE(32, 4) HRIR_QCASE(32, 8) HRIR_QCASE(32, 16) HRIR_QCASE(32, 32) HRIR_QCASE(32, 64)
+    HRIR_QCASE(64, 4) HRIR_QCASE(64, 8) HRIR_QCASE(64, 16) HRIR_QCASE(64, 32) HRIR_QCASE(64, 64)
+#undef HRIR_QCASE
+    return fail(HRIR_EINVAL, "no quad kernel for lf pad %d, k pad %d", lfp, kp);
+}
+
+int quad_prepare(int lfp, int kp, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid) {
+    return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
+        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        const void* kt = reinterpret_cast<const void*>(&k_render_quad<LV, KV>);
+        const void* kpers = reinterpret_cast<const void*>(&k_render_quad_persistent<LV, KV>);
+        hipError_t e = hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(kpers, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
+        if (!persistent) {
+            *grid = (int)n_tiles;
+            return HRIR_OK;
+        }
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, kThreads, lds_bytes);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
+        *grid = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, std::max<int64_t>(n_tiles, 1));
+        return HRIR_OK;
+    });
+}
+
+int quad_launch(int lfp, int kp, bool persistent, int grid, size_t lds_bytes, hipStream_t st, const float* src,
+                const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r, const int* P,
+                const float* Gv, float* out, int lg, int TB, int* ctr) {
+    return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
+        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        if (persistent)
+            hipLaunchKernelGGL((k_render_quad_persistent<LV, KV>), dim3(grid), dim3(kThreads), lds_bytes, st, src,
+                               tiles, n_tiles, jobs, r, P, Gv, out, lg, TB, ctr);
+        else
+            hipLaunchKernelGGL((k_render_quad<LV, KV>), dim3((unsigned)n_tiles), dim3(kThreads), lds_bytes, st, src,
+                               tiles, jobs, r, P, Gv, out, lg, TB);
+        return HRIR_OK;
+    });
+}
+
+}  // namespace hrir

@@ -77,9 +77,10 @@ def test_config0_end_to_end(dev):
     print(f"config0 worst rel L2 {worst:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("kernel", ["quad", "lds_gather", "regwin"])
 @pytest.mark.parametrize("lf,lg,k", [(32, 169, 16), (1, 1, 1), (5, 2, 2), (17, 40, 3), (33, 300, 32),
-                                     (64, 2048, 64), (16, 169, 8), (32, 169, 64)])
-def test_ragged_lengths_and_shapes(dev, lf, lg, k):
+                                     (64, 2048, 64), (16, 169, 8), (32, 169, 64), (64, 169, 33)])
+def test_ragged_lengths_and_shapes(dev, lf, lg, k, kernel):
     h = H()
     rng = np.random.default_rng(lf * 1000 + lg + k)
     r = rng.standard_normal(lf).astype(np.float32)
@@ -92,8 +93,11 @@ def test_ragged_lengths_and_shapes(dev, lf, lg, k):
     lens = [1, 2, 31, 199, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 10000]
     srcs = [synth.white(100 + i, n) for i, n in enumerate(lens)]
     jobs = [(i, (i + j) % F) for i in range(len(lens)) for j in range(2)]
+    if kernel == "regwin" and lg > 169:
+        pytest.skip("the register-window kernel serves lg <= 169")
     plan = h.Plan(r, p, g, lg)
-    rows = render_rows(plan, srcs, jobs, dev)
+    flags = {"quad": 0, "lds_gather": h.SPCONV_LDS_GATHER, "regwin": h.SPCONV_REGWIN}[kernel]
+    rows = render_rows(plan, srcs, jobs, dev, flags=flags)
     check(rows, oracle_rows(r, srcs, p, g, lg, jobs))
 
 
@@ -114,9 +118,13 @@ def test_launch_variants_bitwise_identical(dev):
     plan, r, p, g, lg, srcs, jobs = _variant_setup()
     base = render_rows(plan, srcs, jobs, dev)
     check(base, oracle_rows(r, srcs, p, g, lg, jobs))
-    variants = [dict(tile=1024), dict(tile=2048), dict(tile=8192), dict(tile=16384), dict(group=1),
-                dict(group=3), dict(flags=h.SPCONV_PERSISTENT), dict(flags=h.SPCONV_PERSISTENT, tile=2048),
-                dict(flags=h.SPCONV_UNFUSED), dict(flags=h.SPCONV_PERSISTENT, reps=3)]
+    L, R, PS = h.SPCONV_LDS_GATHER, h.SPCONV_REGWIN, h.SPCONV_PERSISTENT
+    variants = [dict(tile=1024), dict(tile=2048), dict(tile=3072), dict(group=1), dict(group=3),
+                dict(flags=PS), dict(flags=PS, tile=2048, reps=3),
+                dict(flags=L), dict(flags=L, tile=1024), dict(flags=L, tile=8192), dict(flags=L, tile=16384),
+                dict(flags=L, group=3), dict(flags=L | PS), dict(flags=L | PS, tile=2048, reps=3),
+                dict(flags=R), dict(flags=R, tile=12288), dict(flags=R, group=3), dict(flags=R | PS, reps=3),
+                dict(flags=h.SPCONV_UNFUSED)]
     for v in variants:
         rows = render_rows(plan, srcs, jobs, dev, **v)
         for a, b in zip(rows, base):
@@ -132,7 +140,8 @@ def test_graph_replays_match_eager(dev):
     off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
     src = torch.from_numpy(np.concatenate(srcs)).to(dev)
     out_off, total = h.row_layout(plan, lens, jobs)
-    for flags in (h.SPCONV_GRAPH, h.SPCONV_GRAPH | h.SPCONV_PERSISTENT):
+    for flags in (h.SPCONV_GRAPH, h.SPCONV_GRAPH | h.SPCONV_PERSISTENT, h.SPCONV_GRAPH | h.SPCONV_LDS_GATHER,
+                  h.SPCONV_GRAPH | h.SPCONV_REGWIN | h.SPCONV_PERSISTENT):
         out = torch.zeros(total, dtype=torch.float32, device=dev)
         b = h.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], flags=flags)
         for rep in range(4):
@@ -185,7 +194,10 @@ def test_argument_errors(dev):
     lens = np.array([len(s) for s in srcs], dtype=np.int64)
     off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
     for bad_jobs, kw in [([(9, 0, 0)], {}), ([(0, 99, 0)], {}), ([(0, 0, -1)], {}), ([(0, 0, 0)], {"tile": 1000}),
-                         ([(0, 0, 0)], {"tile": 32768}),
+                         ([(0, 0, 0)], {"tile": 32768}), ([(0, 0, 0)], {"tile": 8192}),
+                         ([(0, 0, 0)], {"tile": 1000, "flags": h.SPCONV_LDS_GATHER}),
+                         ([(0, 0, 0)], {"tile": 4096, "flags": h.SPCONV_REGWIN}),
+                         ([(0, 0, 0)], {"flags": h.SPCONV_REGWIN | h.SPCONV_LDS_GATHER}),
                          ([(0, 0, 0)], {"flags": h.SPCONV_PERSISTENT | h.SPCONV_UNFUSED})]:
         with pytest.raises(h.HrirError) as e:
             h.Batch(plan, off, lens, bad_jobs, **kw)
@@ -198,8 +210,11 @@ def test_argument_errors(dev):
     with pytest.raises(h.HrirError) as e:
         b.render(src, small)                                               # row does not fit
     assert "too small" in str(e.value)
-    with pytest.raises(h.HrirError):
+    b.close()
+    b = h.Batch(plan, off, lens, [(len(lens) - 1, 0, 0)])                # reads the last source
+    with pytest.raises(h.HrirError) as e:
         b.render(src[:-1], torch.zeros(10 ** 6, dtype=torch.float32, device=dev))
+    assert "too small" in str(e.value)
     b.close()
 
 
