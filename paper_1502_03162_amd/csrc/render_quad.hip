@@ -82,12 +82,20 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
         }
     }
     __syncthreads();                            // every read of s_win is done
-    // Zc[m] = z_win[m + c] for m < TB + H
+    // Zc[m] = z_win[m + c] for m < TB + H; interior groups of 8 without tests
     const int mlim = TB + H;
 #pragma unroll
     for (int ps = 0; ps < kQMaxPass; ++ps) {
         const int u0 = (ps * kThreads + tid) * kZpt;
-        if (u0 < nz8) {
+        if (u0 >= 4 && u0 + kZpt <= mlim) {
+            float* z0 = zc + u0;
+            *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);
+            *reinterpret_cast<float4*>(z0 + 4) = make_float4(zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c)
+#pragma unroll
+                for (int a = 0; a < kZpt; ++a) zc[c * CS + u0 + a - c] = zz[ps][a];
+        } else if (u0 < nz8) {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -99,68 +107,83 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
     }
     __syncthreads();
 
-    // gather: (job, chunk) pairs round-robin over the waves
+    // gather.  With at least one job per wave, a wave renders whole jobs
+    // (job q = wave, wave + 4, ..., every chunk of it) so a job's taps are
+    // loaded once per tile; with fewer jobs the (job, chunk) pairs go
+    // round-robin so that every wave has work.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int tile_len = min(TB, td.out_len - td.t0);
     const int nchunk = (tile_len + kQChunk - 1) / kQChunk;
-    const int npairs = td.job_count * nchunk;
-    for (int pi = wave; pi < npairs; pi += kWaves) {
-        const int q = pi / nchunk;
-        const int ch = pi - q * nchunk;
-        const JobDesc jd = jobs[td.job_begin + q];
+    int pk[KP];
+    float gk[KP];
+    auto load_taps = [&](const JobDesc& jd) {
         const int* pp = P + (int64_t)jd.filt * KP;
         const float* gg = Gv + (int64_t)jd.filt * KP;
-        int pk[KP];
-        float gk[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) { pk[k] = pp[k]; gk[k] = gg[k]; }
-        float acc[kQR];
+    };
+    auto render_chunk = [&](const JobDesc& jd, int ch) {
+            float acc[kQR];
 #pragma unroll
-        for (int j = 0; j < kQR; ++j) acc[j] = 0.0f;
-        const float* zl = zc + ch * kQChunk + 4 * lane;
-        // Two-stage pipeline as in the other LDS kernel: reads of tap k+1 in
-        // flight during the fmas of tap k; pin16 keeps the compiler from
-        // hoisting every tap's reads.
-        float4 zv[2][4];
-        {
-            const int c = (H - pk[0]) & 3;
-            const float* a = zl + c * CS + (H - pk[0] - c);
+            for (int j = 0; j < kQR; ++j) acc[j] = 0.0f;
+            const float* zl = zc + ch * kQChunk + 4 * lane;
+            // Two-stage pipeline as in the other LDS kernel: reads of tap k+1 in
+            // flight during the fmas of tap k; pin16 keeps the compiler from
+            // hoisting every tap's reads.
+            float4 zv[2][4];
+            {
+                const int c = (H - pk[0]) & 3;
+                const float* a = zl + c * CS + (H - pk[0] - c);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) zv[0][j] = *reinterpret_cast<const float4*>(a + 256 * j);
-        }
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            if (k + 1 < KP) {
-                const int c = (H - pk[k + 1]) & 3;
-                const float* a = zl + c * CS + (H - pk[k + 1] - c);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) zv[(k + 1) & 1][j] = *reinterpret_cast<const float4*>(a + 256 * j);
+                for (int j = 0; j < 4; ++j) zv[0][j] = *reinterpret_cast<const float4*>(a + 256 * j);
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 v = zv[k & 1][j];
-                acc[4 * j + 0] = fmaf(gk[k], v.x, acc[4 * j + 0]);
-                acc[4 * j + 1] = fmaf(gk[k], v.y, acc[4 * j + 1]);
-                acc[4 * j + 2] = fmaf(gk[k], v.z, acc[4 * j + 2]);
-                acc[4 * j + 3] = fmaf(gk[k], v.w, acc[4 * j + 3]);
-            }
-            pin16(acc);
-        }
-        float* orow = out + jd.out_off + td.t0 + ch * kQChunk;
-        const int lim = tile_len - ch * kQChunk;    // valid outputs in this chunk (uniform)
-        if (lim >= kQChunk && ((reinterpret_cast<uintptr_t>(orow) & 15) == 0)) {
+            for (int k = 0; k < KP; ++k) {
+                if (k + 1 < KP) {
+                    const int c = (H - pk[k + 1]) & 3;
+                    const float* a = zl + c * CS + (H - pk[k + 1] - c);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                *reinterpret_cast<float4*>(orow + 4 * lane + 256 * j) =
-                    make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int qo = 4 * lane + 256 * j + i;
-                    if (qo < lim) orow[qo] = acc[4 * j + i];
+                    for (int j = 0; j < 4; ++j) zv[(k + 1) & 1][j] = *reinterpret_cast<const float4*>(a + 256 * j);
                 }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 v = zv[k & 1][j];
+                    acc[4 * j + 0] = fmaf(gk[k], v.x, acc[4 * j + 0]);
+                    acc[4 * j + 1] = fmaf(gk[k], v.y, acc[4 * j + 1]);
+                    acc[4 * j + 2] = fmaf(gk[k], v.z, acc[4 * j + 2]);
+                    acc[4 * j + 3] = fmaf(gk[k], v.w, acc[4 * j + 3]);
+                }
+                pin16(acc);
+            }
+            float* orow = out + jd.out_off + td.t0 + ch * kQChunk;
+            const int lim = tile_len - ch * kQChunk;    // valid outputs in this chunk (uniform)
+            if (lim >= kQChunk && ((reinterpret_cast<uintptr_t>(orow) & 15) == 0)) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    *reinterpret_cast<float4*>(orow + 4 * lane + 256 * j) =
+                        make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int qo = 4 * lane + 256 * j + i;
+                        if (qo < lim) orow[qo] = acc[4 * j + i];
+                    }
+            }
+    };
+    if (td.job_count >= kWaves) {
+        for (int q = wave; q < td.job_count; q += kWaves) {
+            const JobDesc jd = jobs[td.job_begin + q];
+            load_taps(jd);
+            for (int ch = 0; ch < nchunk; ++ch) render_chunk(jd, ch);
+        }
+    } else {
+        for (int it = wave; it < td.job_count * nchunk; it += kWaves) {
+            const int q = it / nchunk;
+            const JobDesc jd = jobs[td.job_begin + q];
+            load_taps(jd);
+            render_chunk(jd, it - q * nchunk);
         }
     }
 }
