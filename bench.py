@@ -113,6 +113,9 @@ def main():
                     help="fused render kernel (quad: default)")
     ap.add_argument("--cpu-sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="dense,fft", help="comparison legs to time: dense, fft (comma list, or none)")
+    ap.add_argument("--leg-steps", type=int, default=5)
+    ap.add_argument("--fft-sizes", default="1024,4096,16384")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
@@ -161,6 +164,32 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"sparse K={args.k}: {ms:.3f} ms/step, {value:.4g} samples/s, {achieved:.0f} GB/s algorithmic")
 
+    # comparison legs on the same GPU, same sources and rows (a dense row has
+    # the same length: 200-tap HRIR, src_len + 199)
+    legs = {}
+    want = [x for x in args.legs.split(",") if x and x != "none"]
+    if "dense" in want:
+        dplan = H.DensePlan(hs.h.astype(np.float32))
+        dbatch = H.DenseBatch(dplan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)])
+        dms, _ = time_launches(lambda: dbatch.render(src, out), args.leg_steps, 1)
+        legs["dense_200"] = {"ms_per_step": dms, "value": n_out / (dms * 1e-3), "kernel": "k_dense",
+                             "speedup_sparse": dms / ms}
+        log(f"dense 200-tap: {dms:.3f} ms/step, {n_out / (dms * 1e-3):.4g} samples/s, sparse speedup {dms / ms:.2f}x")
+        dbatch.close()
+        dplan.close()
+    if "fft" in want:
+        by = {}
+        for nfft in [int(x) for x in args.fft_sizes.split(",") if x]:
+            fo = H.FftOla(hs.h.astype(np.float32), nfft, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)])
+            fms, _ = time_launches(lambda: fo.render(src, out), args.leg_steps, 1)
+            by[str(nfft)] = fms
+            log(f"FFT overlap-add nfft={nfft}: {fms:.3f} ms/step, {n_out / (fms * 1e-3):.4g} samples/s")
+            fo.close()
+            torch.cuda.empty_cache()
+        best = min(by, key=by.get)
+        legs["fft_ola"] = {"ms_per_step": by[best], "value": n_out / (by[best] * 1e-3), "best_nfft": int(best),
+                           "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -186,6 +215,7 @@ def main():
                                 "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters},
+        "legs": legs,
         "wall_s_timed": wall,
     }
     del out

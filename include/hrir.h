@@ -179,6 +179,50 @@ int spconv_render(const hrir_plan* plan, const float* d_src, int64_t src_elems, 
                   const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs,
                   float* d_out, int64_t out_elems, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Dense direct render: the comparison leg, out = s * h with a full HRIR
+ * (direct convolution costs the filter length per output, Sec. IV-F).
+ *
+ * dense_plan   h host f32[n_filters][m], 1 <= m <= 200, copied to the device.
+ * dense_batch_create / _render / _destroy: as spconv_batch_*, with output
+ *              rows of length src_len + m - 1 at each job's out_off.
+ * Errors: EINVAL (ranges, non-finite h, buffers too small), ENOMEM, EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct hrir_dense hrir_dense;
+typedef struct hrir_dense_batch hrir_dense_batch;
+
+int dense_plan(const float* h, int32_t n_filters, int32_t m, hrir_dense** out);
+void dense_plan_destroy(hrir_dense* plan);
+int dense_batch_create(const hrir_dense* plan, const int64_t* src_off, const int64_t* src_len, int32_t n_src,
+                       const spconv_job* jobs, int32_t n_jobs, hrir_dense_batch** out);
+int dense_batch_render(hrir_dense_batch* batch, const float* d_src, int64_t src_elems, float* d_out,
+                       int64_t out_elems, void* stream);
+void dense_batch_destroy(hrir_dense_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Partitioned FFT convolution, overlap-add form: the frequency-domain
+ * comparison leg (FFT convolution, Sec. I; block form and cost, Sec. IV-F).
+ *
+ * fftola_create  h host f32[n_filters][m]; nfft a power of two, 2m <= nfft
+ *                <= 2^20; blocks of nfft - m + 1 source samples.  Plans the
+ *                batched transforms (hipFFT), computes the spectra of the used
+ *                filters and allocates the block buffers for this job list
+ *                (rows as in dense_batch_*).  Synchronous.
+ * fftola_render  enqueues block gather, R2C, spectrum products, C2R and the
+ *                overlap-add on `stream`.
+ * fftola_info    host int64[4]: nfft, block length, source blocks, (job,
+ *                block) pairs.
+ * Errors: EINVAL, ENOMEM, EDEVICE (hipFFT failures included).
+ * ---------------------------------------------------------------------- */
+typedef struct hrir_fft hrir_fft;
+
+int fftola_create(const float* h, int32_t n_filters, int32_t m, int32_t nfft, const int64_t* src_off,
+                  const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs, hrir_fft** out);
+int fftola_render(hrir_fft* plan, const float* d_src, int64_t src_elems, float* d_out, int64_t out_elems,
+                  void* stream);
+int fftola_info(const hrir_fft* plan, int64_t* info4);
+void fftola_destroy(hrir_fft* plan);
+
 #ifdef __cplusplus
 }
 #endif

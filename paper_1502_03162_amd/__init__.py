@@ -39,9 +39,20 @@ class SpconvJob(ctypes.Structure):
     _fields_ = [("src", c_int32), ("filt", c_int32), ("out_off", c_int64)]
 
 
+def _preload_torch_fft():
+    """Load torch's hipFFT first (same soname as ROCm's), so the library's
+    FFT leg runs on the FFT stack that matches torch's HIP runtime."""
+    libdir = os.path.join(os.path.dirname(torch.__file__), "lib")
+    for name in ("librocfft.so", "libhipfft.so"):
+        path = os.path.join(libdir, name)
+        if os.path.exists(path):
+            ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1502_03162_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python paper_1502_03162_amd/build.py`")
+    _preload_torch_fft()
     lib = ctypes.CDLL(LIB_PATH)
     P_d, P_f, P_i32, P_i64 = POINTER(c_double), POINTER(c_float), POINTER(c_int32), POINTER(c_int64)
     sig = {
@@ -57,6 +68,17 @@ def _load() -> ctypes.CDLL:
         "spconv_batch_destroy": (None, [c_void_p]),
         "spconv_render": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
                                   c_void_p, c_int64, c_void_p]),
+        "dense_plan": (c_int, [P_f, c_int32, c_int32, POINTER(c_void_p)]),
+        "dense_plan_destroy": (None, [c_void_p]),
+        "dense_batch_create": (c_int, [c_void_p, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
+                                       POINTER(c_void_p)]),
+        "dense_batch_render": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
+        "dense_batch_destroy": (None, [c_void_p]),
+        "fftola_create": (c_int, [P_f, c_int32, c_int32, c_int32, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
+                                  POINTER(c_void_p)]),
+        "fftola_render": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
+        "fftola_info": (c_int, [c_void_p, P_i64]),
+        "fftola_destroy": (None, [c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -67,7 +89,9 @@ def _load() -> ctypes.CDLL:
 
 _lib = _load()
 EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_destroy", "spconv_batch_create",
-            "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render")
+            "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "dense_plan",
+            "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
+            "fftola_render", "fftola_info", "fftola_destroy")
 
 
 def lib() -> ctypes.CDLL:
@@ -231,3 +255,97 @@ def render(plan: Plan, src, src_off, src_len, jobs, out, stream=None):
     op, on = _f32(out)
     _check(_lib.spconv_render(plan.handle, sp, sn, _ptr(src_off, c_int64), _ptr(src_len, c_int64), src_len.size,
                               jobs, n, op, on, c_void_p(_stream_handle(stream))))
+
+
+# ---------------------------------------------------------------------------
+# Dense direct render (comparison leg)
+# ---------------------------------------------------------------------------
+class DensePlan:
+    """Full HRIRs h [n_filters][m] (m <= 200) resident on the device."""
+
+    def __init__(self, h):
+        h = np.ascontiguousarray(h, dtype=np.float32)
+        if h.ndim != 2:
+            raise ValueError("h must be [n_filters][m]")
+        self.n_filters, self.m = h.shape
+        hd = c_void_p()
+        _check(_lib.dense_plan(_ptr(h, c_float), h.shape[0], h.shape[1], byref(hd)))
+        self._h = hd
+
+    @property
+    def handle(self):
+        return self._h
+
+    def out_len(self, src_len: int) -> int:
+        return int(src_len) + self.m - 1
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dense_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class DenseBatch:
+    def __init__(self, plan: DensePlan, src_off, src_len, jobs):
+        self.plan = plan
+        self.src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+        self.src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+        jobs, n = make_jobs(jobs)
+        self._jobs = jobs
+        hd = c_void_p()
+        _check(_lib.dense_batch_create(plan.handle, _ptr(self.src_off, c_int64), _ptr(self.src_len, c_int64),
+                                       self.src_len.size, jobs, n, byref(hd)))
+        self._h = hd
+
+    def render(self, src, out, stream=None):
+        sp, sn = _f32(src)
+        op, on = _f32(out)
+        _check(_lib.dense_batch_render(self._h, sp, sn, op, on, c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dense_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+# ---------------------------------------------------------------------------
+# Partitioned FFT convolution, overlap-add (comparison leg)
+# ---------------------------------------------------------------------------
+class FftOla:
+    """Overlap-add FFT convolution of a fixed job list (hipFFT transforms)."""
+
+    def __init__(self, h, nfft: int, src_off, src_len, jobs):
+        h = np.ascontiguousarray(h, dtype=np.float32)
+        self.n_filters, self.m = h.shape
+        self.src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+        self.src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+        jobs, n = make_jobs(jobs)
+        self._jobs = jobs
+        hd = c_void_p()
+        _check(_lib.fftola_create(_ptr(h, c_float), h.shape[0], h.shape[1], nfft, _ptr(self.src_off, c_int64),
+                                  _ptr(self.src_len, c_int64), self.src_len.size, jobs, n, byref(hd)))
+        self._h = hd
+
+    def out_len(self, src_len: int) -> int:
+        return int(src_len) + self.m - 1
+
+    def info(self) -> dict:
+        a = np.zeros(4, dtype=np.int64)
+        _check(_lib.fftola_info(self._h, _ptr(a, c_int64)))
+        return {"nfft": int(a[0]), "block": int(a[1]), "source_blocks": int(a[2]), "job_blocks": int(a[3])}
+
+    def render(self, src, out, stream=None):
+        sp, sn = _f32(src)
+        op, on = _f32(out)
+        _check(_lib.fftola_render(self._h, sp, sn, op, on, c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fftola_destroy(self._h)
+            self._h = None
+
+    __del__ = close

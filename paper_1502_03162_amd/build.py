@@ -1,6 +1,7 @@
 """Build libhrir.so (HIP for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1502_03162_amd.build
+Usage: python paper_1502_03162_amd/build.py   (runs without importing the
+package, which needs the library this script produces)
 """
 from __future__ import annotations
 
@@ -13,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
-SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "factorize.cpp", "errors.cpp"]
+SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "factorize.cpp",
+           "errors.cpp"]
 
 # Per-file extra flags.  The register-window kernel dispatches taps through a
 # tree of wave-uniform scalar branches; the structurizer must leave such
