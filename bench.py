@@ -99,6 +99,49 @@ def cpu_baseline(r, srcs, p, g, lg, jobs, n_src_sample: int, chunk: int = 4):
                       f"({n_out} outputs), FP64 oracle in chunks of {chunk} sources, {dt:.1f} s"}
 
 
+def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
+    """Uneven batching: 512 pink sources with lengths log-uniform in
+    [4096, 1048576], each at 1..8 random directions x 2 ears of the same
+    1,250-direction set, K = 16, all in one persistent launch replayed from a
+    HIP graph, tile shape from the autotuner."""
+    import synth
+    n_src = 512
+    lens = synth.uneven_lengths(300, n_src)
+    jobs = [(int(a), int(b)) for a, b in synth.jobs_uneven(300, n_src, 1250)]
+    log(f"uneven: {n_src} sources, {int(lens.sum())} samples, {len(jobs)} rows")
+    srcs = [synth.pink(1000 + i, int(n)) for i, n in enumerate(lens)]
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    plan = H.Plan(r, fac["p"], fac["g"], lg)
+    src = torch.from_numpy(np.concatenate(srcs)).to(dev)
+    out_off, total = H.row_layout(plan, lens, jobs)
+    out = torch.empty(total, dtype=torch.float32, device=dev)
+    rows = [(s, f, o) for (s, f), o in zip(jobs, out_off)]
+    t0 = time.perf_counter()
+    best = H.autotune(plan, src, off, lens, rows, out, force_flags=H.SPCONV_PERSISTENT)
+    free_best = H.autotune(plan, src, off, lens, rows, out)
+    tune_s = time.perf_counter() - t0
+    batch = H.Batch(plan, off, lens, rows, tile=best["tile"], group=best["group"],
+                    flags=best["flags"] | H.SPCONV_GRAPH)
+    n_out = sum(plan.out_len(lens[s]) for s, _ in jobs)
+    ms, _ = time_launches(lambda: batch.render(src, out), args.steps, args.warmup)
+    alg = 4.0 * n_out + 4.0 * float(lens.sum())
+    log(f"uneven: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s, tile {best['tile']} group {best['group']} "
+        f"(autotune {tune_s:.1f} s, best candidate {best['ms']:.3f} ms)")
+    info = batch.info()
+    batch.close()
+    del out, src
+    torch.cuda.empty_cache()
+    return {"workload": "512 pink sources, lengths log-uniform in [4096, 1048576], 1..8 directions x 2 ears, K=16, "
+                        "one persistent launch replayed from a HIP graph",
+            "output_samples": n_out, "rows": len(jobs), "ms_per_step": ms, "value": n_out / (ms * 1e-3),
+            "unit": "output samples/s", "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
+            "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile": best["tile"], "group": best["group"],
+            "persistent_grid": info["grid"], "tiles": info["tiles"], "autotune_s": tune_s,
+            "best_any_shape": {"tile": free_best["tile"], "group": free_best["group"],
+                               "persistent": bool(free_best["flags"] & H.SPCONV_PERSISTENT),
+                               "ms_per_step": free_best["ms"]}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +159,7 @@ def main():
     ap.add_argument("--legs", default="dense,fft", help="comparison legs to time: dense, fft (comma list, or none)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
@@ -190,6 +234,8 @@ def main():
         legs["fft_ola"] = {"ms_per_step": by[best], "value": n_out / (by[best] * 1e-3), "best_nfft": int(best),
                            "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
 
+    uneven = None if args.no_uneven else bench_uneven(H, torch, dev, fac, r, lf, lg, args)
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -216,6 +262,7 @@ def main():
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters},
         "legs": legs,
+        "uneven": uneven,
         "wall_s_timed": wall,
     }
     del out

@@ -101,6 +101,8 @@ typedef struct hrir_plan hrir_plan;
 int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
                 int32_t k, int32_t lg, hrir_plan** out);
 void spconv_plan_destroy(hrir_plan* plan);
+/* host int32[3]: lf, k, lg of the plan. */
+int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3);
 
 /* One render job: source `src` through filter `filt` into one output row of
  * length src_len[src] + lf + lg - 2 starting at element out_off of the
@@ -171,6 +173,23 @@ int spconv_batch_render(hrir_batch* batch, const float* d_src, int64_t src_elems
  * (0 quad, 1 register window, 2 LDS gather, 3 unfused). */
 int spconv_batch_info(const hrir_batch* batch, int64_t* info5);
 void spconv_batch_destroy(hrir_batch* batch);
+
+/* Autotuner: for this job list, time every (tile, group, persistent) shape
+ * the default kernel accepts (tile 1024..4096, group 0/4/8/16) with HIP
+ * events, 1 warm-up + 3 timed renders each on `stream`, and return the
+ * fastest (tile, group, flags) and its ms per render.  force_flags
+ * (SPCONV_PERSISTENT and/or SPCONV_LDS_GATHER, or 0) is part of every
+ * candidate; with SPCONV_PERSISTENT only persistent shapes are timed.  d_out is used as
+ * scratch output (every job row is overwritten).  With cache_path (JSON,
+ * may not exist yet) a result stored under the same key (K, lf, lg and the
+ * job list's shape class: log2 of the output samples, jobs per source, log2
+ * of the sources, force_flags) is returned without timing, and new results
+ * are stored.
+ * Synchronous.  Errors: EINVAL, EDEVICE. */
+int spconv_autotune(const hrir_plan* plan, const float* d_src, int64_t src_elems, const int64_t* src_off,
+                    const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs, float* d_out,
+                    int64_t out_elems, void* stream, const char* cache_path, int32_t force_flags,
+                    int32_t* tile_out, int32_t* group_out, int32_t* flags_out, double* ms_out);
 
 /* One-shot render: create a batch with default tiling, render it on
  * `stream`, wait for the stream, destroy the batch.  Synchronous.  Same

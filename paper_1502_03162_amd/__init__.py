@@ -79,6 +79,9 @@ def _load() -> ctypes.CDLL:
         "fftola_render": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
         "fftola_info": (c_int, [c_void_p, P_i64]),
         "fftola_destroy": (None, [c_void_p]),
+        "spconv_plan_shape": (c_int, [c_void_p, P_i32]),
+        "spconv_autotune": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
+                                    c_void_p, c_int64, c_void_p, c_char_p, c_int32, P_i32, P_i32, P_i32, P_d]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -91,7 +94,7 @@ _lib = _load()
 EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_destroy", "spconv_batch_create",
             "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "dense_plan",
             "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
-            "fftola_render", "fftola_info", "fftola_destroy")
+            "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune")
 
 
 def lib() -> ctypes.CDLL:
@@ -244,6 +247,24 @@ class Batch:
             self._h = None
 
     __del__ = close
+
+
+def autotune(plan: Plan, src, src_off, src_len, jobs, out, cache_path=None, force_flags: int = 0,
+             stream=None) -> dict:
+    """Fastest (tile, group, flags) for this job list (spconv_autotune);
+    overwrites `out`'s job rows while timing."""
+    src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+    src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+    jobs, n = make_jobs(jobs)
+    sp, sn = _f32(src)
+    op, on = _f32(out)
+    t, g, f = c_int32(), c_int32(), c_int32()
+    ms = c_double()
+    _check(_lib.spconv_autotune(plan.handle, sp, sn, _ptr(src_off, c_int64), _ptr(src_len, c_int64), src_len.size,
+                                jobs, n, op, on, c_void_p(_stream_handle(stream)),
+                                None if cache_path is None else os.fsencode(cache_path), force_flags, byref(t),
+                                byref(g), byref(f), byref(ms)))
+    return {"tile": t.value, "group": g.value, "flags": f.value, "ms": ms.value}
 
 
 def render(plan: Plan, src, src_off, src_len, jobs, out, stream=None):

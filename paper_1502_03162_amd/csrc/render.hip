@@ -360,6 +360,15 @@ extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const f
     return HRIR_OK;
 }
 
+extern "C" int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3) {
+    clear_error();
+    if (!plan || !lf_k_lg3) return fail(HRIR_EINVAL, "spconv_plan_shape: null pointer");
+    lf_k_lg3[0] = plan->lf;
+    lf_k_lg3[1] = plan->k;
+    lf_k_lg3[2] = plan->lg;
+    return HRIR_OK;
+}
+
 extern "C" void spconv_plan_destroy(hrir_plan* plan) {
     if (!plan) return;
     (void)hipFree(plan->d_r);
@@ -452,6 +461,13 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         }
         j0 = j1;
     }
+    // Largest work first: the hardware dispatcher (or the persistent queue)
+    // then finishes a ragged job mix with small tiles at the end.
+    std::stable_sort(ht.begin(), ht.end(), [tile](const TileDesc& a, const TileDesc& c) {
+        const int64_t wa = (int64_t)a.job_count * std::min<int64_t>(tile, a.out_len - a.t0);
+        const int64_t wc = (int64_t)c.job_count * std::min<int64_t>(tile, c.out_len - c.t0);
+        return wa > wc;
+    });
     b->n_tiles = (int64_t)ht.size();
     b->group = max_group;
     b->lds_bytes = kind == KIND_REGWIN ? (size_t)rw_lds_bytes(tile, plan->lfp)
