@@ -142,6 +142,64 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
                                "ms_per_step": free_best["ms"]}}
 
 
+def bench_latency(H, torch, dev, fac, r, lg, args):
+    """Block latency: 1,024 streams; each launch renders one block of
+    U{64..1024} samples per stream (both ears of a random direction) with the
+    stream histories on the device.  HIP events bracket each block_render
+    call (its host-side check and job-table upload, then the kernel); job
+    tables are built before the bracket.  Inputs are resident in HBM."""
+    import synth
+    n_streams, ticks = 1024, args.latency_ticks
+    rng = np.random.default_rng(77)
+    plan = H.Plan(r, fac["p"], fac["g"], lg)
+    st = H.Streams(plan, n_streams)
+    pool_len = 4 << 20
+    pool = torch.from_numpy(synth.pink(4242, pool_len)).to(dev)
+    out = torch.empty(2 * 1024 * n_streams, dtype=torch.float32, device=dev)
+    sizes = rng.integers(64, 1025, size=(ticks, n_streams))
+    dirs = rng.integers(0, 1250, size=(ticks, n_streams))
+    starts = rng.integers(0, pool_len - 1024, size=(ticks, n_streams))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(ticks)]
+    cur = torch.cuda.current_stream()
+
+    def table(t):
+        jt = np.zeros(n_streams, dtype=H.BLOCK_JOB_DTYPE)
+        jt["stream_id"] = np.arange(n_streams)
+        jt["n"] = sizes[t]
+        jt["filt_l"] = 2 * dirs[t]
+        jt["filt_r"] = 2 * dirs[t] + 1
+        jt["in_off"] = starts[t]
+        jt["out_off"] = np.concatenate([[0], np.cumsum(2 * sizes[t])[:-1]])
+        return jt
+
+    for t in range(min(ticks, 20)):                      # warm-up launches
+        st.render(pool, table(t), out)
+    torch.cuda.synchronize()
+    samples = 0
+    t0 = time.perf_counter()
+    for t in range(ticks):
+        jt = table(t)
+        samples += 2 * int(sizes[t].sum())
+        ev[t][0].record(cur)
+        st.render(pool, jt, out)
+        ev[t][1].record(cur)
+        if t % 2000 == 1999:
+            log(f"latency: {t + 1} launches")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    st.close()
+    res = {"streams": n_streams, "launches": ticks, "block_samples": "U{64..1024} per stream per launch",
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "gpu_samples_per_s": samples / (lat.sum() * 1e-3),
+           "wall_samples_per_s": samples / wall,
+           "note": "per launch: HIP events around block_render (host-side check and job-table upload, then the "
+                   "kernel); wall_samples_per_s also includes building the job tables in Python"}
+    log(f"block latency: p50 {res['p50_ms'] * 1e3:.1f} us, p99 {res['p99_ms'] * 1e3:.1f} us, "
+        f"{res['gpu_samples_per_s']:.3g} output samples/s on the GPU")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +218,7 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
+    ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
@@ -235,6 +294,7 @@ def main():
                            "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
 
     uneven = None if args.no_uneven else bench_uneven(H, torch, dev, fac, r, lf, lg, args)
+    latency = bench_latency(H, torch, dev, fac, r, lg, args) if args.latency_ticks > 0 else None
 
     res = {
         "metric": METRIC,
@@ -263,6 +323,7 @@ def main():
                     "fact_iters": args.fact_iters},
         "legs": legs,
         "uneven": uneven,
+        "block_latency": latency,
         "wall_s_timed": wall,
     }
     del out

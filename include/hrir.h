@@ -103,6 +103,11 @@ int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, in
 void spconv_plan_destroy(hrir_plan* plan);
 /* host int32[3]: lf, k, lg of the plan. */
 int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3);
+/* The plan's device tables (owned by the plan): r f32[lfp] (zero padded),
+ * p int32[n_filters][kp], g f32[n_filters][kp] (padded with (0, 0)), and
+ * host int32[3] = lfp, kp, n_filters. */
+int spconv_plan_device(const hrir_plan* plan, const float** r, const int** p, const float** g,
+                       int32_t* lfp_kp_nf3);
 
 /* One render job: source `src` through filter `filt` into one output row of
  * length src_len[src] + lf + lg - 2 starting at element out_off of the
@@ -241,6 +246,51 @@ int fftola_render(hrir_fft* plan, const float* d_src, int64_t src_elems, float* 
                   void* stream);
 int fftola_info(const hrir_fft* plan, int64_t* info4);
 void fftola_destroy(hrir_fft* plan);
+
+/* ------------------------------------------------------------------------
+ * Block (partitioned) rendering with device-resident stream history: the
+ * real-time form (Sec. IV-F: time-domain partitioned convolution adds no
+ * latency).  Each stream slot keeps the last lf - 1 source samples and the
+ * last lg - 1 values of z = f * s in device memory; rendering a block emits
+ * the block's output samples for both ears (sample t with input sample t)
+ * and updates the slot.  Any split of a stream into blocks, followed by a
+ * flush, reproduces spconv_render of the whole stream bit for bit.
+ *
+ * block_streams_create  max_streams slots (1..2^20), histories zeroed; the
+ *                       plan must outlive the object.
+ * block_streams_reset   zero the listed slots (start of a new stream).
+ * block_render          one launch for n_jobs blocks, at most one per slot.
+ *     d_in      device f32: block i is d_in[in_off, in_off + n), n in
+ *               [1, 4096]; unused for flush blocks (may be null if every
+ *               block is a flush).
+ *     d_out     device f32: block i writes m samples of the left ear
+ *               (filt_l) at out_off and m of the right ear (filt_r) at
+ *               out_off + m; m = n, or lf + lg - 2 for a flush block.
+ *     The job table is staged through pinned host memory (double buffered),
+ *     so the call returns after enqueueing and jobs may be reused at once.
+ * Errors: EINVAL (ranges, a stream twice in one call, buffers too small),
+ * EDEVICE.
+ * ---------------------------------------------------------------------- */
+#define BLOCK_FLUSH 1
+
+typedef struct {
+    int32_t stream_id;   /* slot */
+    int32_t n;           /* input samples (ignored for a flush) */
+    int32_t filt_l;      /* left-ear filter */
+    int32_t filt_r;      /* right-ear filter */
+    int32_t flags;       /* BLOCK_FLUSH: emit the lf + lg - 2 tail samples */
+    int32_t pad;
+    int64_t in_off;
+    int64_t out_off;
+} block_job;
+
+typedef struct hrir_streams hrir_streams;
+
+int block_streams_create(const hrir_plan* plan, int32_t max_streams, hrir_streams** out);
+int block_streams_reset(hrir_streams* streams, const int32_t* slots, int32_t n, void* stream);
+int block_render(hrir_streams* streams, const float* d_in, int64_t in_elems, const block_job* jobs, int32_t n_jobs,
+                 float* d_out, int64_t out_elems, void* stream);
+void block_streams_destroy(hrir_streams* streams);
 
 #ifdef __cplusplus
 }

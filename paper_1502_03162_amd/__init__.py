@@ -39,6 +39,20 @@ class SpconvJob(ctypes.Structure):
     _fields_ = [("src", c_int32), ("filt", c_int32), ("out_off", c_int64)]
 
 
+class BlockJob(ctypes.Structure):
+    _fields_ = [("stream_id", c_int32), ("n", c_int32), ("filt_l", c_int32), ("filt_r", c_int32),
+                ("flags", c_int32), ("pad", c_int32), ("in_off", c_int64), ("out_off", c_int64)]
+
+
+BLOCK_FLUSH = 1
+
+# numpy layout of block_job (40 bytes), for building job tables without a
+# Python loop
+BLOCK_JOB_DTYPE = np.dtype([("stream_id", "<i4"), ("n", "<i4"), ("filt_l", "<i4"), ("filt_r", "<i4"),
+                            ("flags", "<i4"), ("pad", "<i4"), ("in_off", "<i8"), ("out_off", "<i8")])
+assert BLOCK_JOB_DTYPE.itemsize == ctypes.sizeof(BlockJob)
+
+
 def _preload_torch_fft():
     """Load torch's hipFFT first (same soname as ROCm's), so the library's
     FFT leg runs on the FFT stack that matches torch's HIP runtime."""
@@ -80,6 +94,11 @@ def _load() -> ctypes.CDLL:
         "fftola_info": (c_int, [c_void_p, P_i64]),
         "fftola_destroy": (None, [c_void_p]),
         "spconv_plan_shape": (c_int, [c_void_p, P_i32]),
+        "spconv_plan_device": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), P_i32]),
+        "block_streams_create": (c_int, [c_void_p, c_int32, POINTER(c_void_p)]),
+        "block_streams_reset": (c_int, [c_void_p, P_i32, c_int32, c_void_p]),
+        "block_render": (c_int, [c_void_p, c_void_p, c_int64, POINTER(BlockJob), c_int32, c_void_p, c_int64, c_void_p]),
+        "block_streams_destroy": (None, [c_void_p]),
         "spconv_autotune": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
                                     c_void_p, c_int64, c_void_p, c_char_p, c_int32, P_i32, P_i32, P_i32, P_d]),
     }
@@ -94,7 +113,9 @@ _lib = _load()
 EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_destroy", "spconv_batch_create",
             "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "dense_plan",
             "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
-            "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune")
+            "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
+            "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
+            "block_streams_destroy")
 
 
 def lib() -> ctypes.CDLL:
@@ -367,6 +388,55 @@ class FftOla:
     def close(self):
         if getattr(self, "_h", None):
             _lib.fftola_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+# ---------------------------------------------------------------------------
+# Block rendering with device-resident stream history
+# ---------------------------------------------------------------------------
+class Streams:
+    """Per-stream history slots for block rendering (block_streams_*)."""
+
+    def __init__(self, plan: Plan, max_streams: int):
+        self.plan = plan
+        self.max_streams = max_streams
+        self.tail = plan.lf + plan.lg - 2
+        hd = c_void_p()
+        _check(_lib.block_streams_create(plan.handle, max_streams, byref(hd)))
+        self._h = hd
+        self._jobs = (BlockJob * max_streams)()
+
+    def reset(self, slots, stream=None):
+        a = np.ascontiguousarray(slots, dtype=np.int32)
+        _check(_lib.block_streams_reset(self._h, _ptr(a, c_int32), a.size, c_void_p(_stream_handle(stream))))
+
+    def render(self, d_in, jobs, d_out, stream=None):
+        """jobs: a numpy array of BLOCK_JOB_DTYPE, or an iterable of
+        (stream_id, n, filt_l, filt_r, in_off, out_off, flush)."""
+        if isinstance(jobs, np.ndarray):
+            if jobs.dtype != BLOCK_JOB_DTYPE or not jobs.flags.c_contiguous:
+                raise ValueError("job table must be a contiguous BLOCK_JOB_DTYPE array")
+            table, n = jobs.ctypes.data_as(POINTER(BlockJob)), jobs.size
+        else:
+            n = 0
+            for (sid, ln, fl, fr, io, oo, flush) in jobs:
+                j = self._jobs[n]
+                j.stream_id, j.n, j.filt_l, j.filt_r = int(sid), int(ln), int(fl), int(fr)
+                j.flags, j.pad, j.in_off, j.out_off = BLOCK_FLUSH if flush else 0, 0, int(io), int(oo)
+                n += 1
+            table = self._jobs
+        if d_in is None:
+            ip, inn = c_void_p(0), 0
+        else:
+            ip, inn = _f32(d_in)
+        op, on = _f32(d_out)
+        _check(_lib.block_render(self._h, ip, inn, table, n, op, on, c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.block_streams_destroy(self._h)
             self._h = None
 
     __del__ = close

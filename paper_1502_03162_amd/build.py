@@ -14,8 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
-SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "autotune.cpp",
-           "factorize.cpp", "errors.cpp"]
+SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "block.hip",
+           "autotune.cpp", "factorize.cpp", "errors.cpp"]
 
 # Per-file extra flags.  The register-window kernel dispatches taps through a
 # tree of wave-uniform scalar branches; the structurizer must leave such

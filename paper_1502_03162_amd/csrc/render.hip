@@ -369,6 +369,19 @@ extern "C" int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3) {
     return HRIR_OK;
 }
 
+extern "C" int spconv_plan_device(const hrir_plan* plan, const float** r, const int** p, const float** g,
+                                  int32_t* lfp_kp_nf3) {
+    clear_error();
+    if (!plan || !r || !p || !g || !lfp_kp_nf3) return fail(HRIR_EINVAL, "spconv_plan_device: null pointer");
+    *r = plan->d_r;
+    *p = plan->d_p;
+    *g = plan->d_g;
+    lfp_kp_nf3[0] = plan->lfp;
+    lfp_kp_nf3[1] = plan->kp;
+    lfp_kp_nf3[2] = plan->n_filters;
+    return HRIR_OK;
+}
+
 extern "C" void spconv_plan_destroy(hrir_plan* plan) {
     if (!plan) return;
     (void)hipFree(plan->d_r);
