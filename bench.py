@@ -34,8 +34,10 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources of the default render kernel (a counter summary
+    taken on other sources is not reported)."""
     h = hashlib.sha256()
-    for fn in ("render.hip",):
+    for fn in ("render.hip", "render_quad.hip", "render_common.h"):
         h.update(open(os.path.join(ROOT, "paper_1502_03162_amd", "csrc", fn), "rb").read())
     return h.hexdigest()[:16]
 
@@ -219,6 +221,8 @@ def main():
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
     ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run 3 device copies of 1 GiB (read 1 GiB + write 1 GiB each) to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
@@ -293,6 +297,15 @@ def main():
         legs["fft_ola"] = {"ms_per_step": by[best], "value": n_out / (by[best] * 1e-3), "best_nfft": int(best),
                            "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
 
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies done")
+        del a, c
     uneven = None if args.no_uneven else bench_uneven(H, torch, dev, fac, r, lf, lg, args)
     latency = bench_latency(H, torch, dev, fac, r, lg, args) if args.latency_ticks > 0 else None
 
