@@ -292,6 +292,129 @@ int block_render(hrir_streams* streams, const float* d_in, int64_t in_elems, con
                  float* d_out, int64_t out_elems, void* stream);
 void block_streams_destroy(hrir_streams* streams);
 
+/* ------------------------------------------------------------------------
+ * Streaming request loop with continuous batching: the serving form of the
+ * block renderer above (Sec. IV-F; Eq. (2) applied block by block, so each
+ * output sample leaves with its input sample).
+ *
+ * Blocks of many streams are submitted from host memory at any time.  A
+ * loop thread gathers what has arrived into the next launch (a
+ * "generation": at most one block per stream, as a stream's blocks run in
+ * order through its device-resident history) and starts it while fewer than
+ * two generations are on the GPU, so blocks that arrive during a render join
+ * the following one.  Generation buffers (device memory plus pinned host
+ * staging) form a ring sized from hbm_budget; a block that no buffer can
+ * take is refused with HRIR_EAGAIN, never waited for.  The result of every
+ * block is the same bits whatever else shares its launch.
+ *
+ * stream_open    max_streams stream slots (1..2^20) with zeroed histories;
+ *                hbm_budget bounds the device bytes of histories plus the
+ *                generation ring (EINVAL if it cannot hold two generations
+ *                of one maximal block).  flags: STREAM_DIRECT_LAUNCH sizes
+ *                each launch to its batch (one workgroup per block) instead
+ *                of replaying a HIP graph of a persistent launch.  Starts a
+ *                loop thread and a completion thread on the current device.
+ * stream_submit  copies n samples (1..4096) of host_block; the caller keeps
+ *                its buffer.  filt_l/filt_r are the block's left/right
+ *                filters (a direction change takes effect at the block
+ *                boundary).  EAGAIN when no generation buffer has room:
+ *                poll, then submit again.
+ * stream_end     queues the stream's flush: its result carries the last
+ *                lf + lg - 2 output samples (flags STREAM_RESULT_TAIL) and
+ *                the stream's history is zeroed, so the id may start a new
+ *                stream at once.  EAGAIN as for stream_submit.
+ * stream_poll    moves up to max finished results to out[] in completion
+ *                order (per stream, submission order) and returns their
+ *                count.  A result's out points to 2 * n host floats owned by
+ *                the server (left ear, then right ear), valid until the next
+ *                stream_poll call on this server.  timeout_us: 0 returns at
+ *                once, > 0 waits up to that long for a result, < 0 waits
+ *                until one is ready; it never waits when nothing is queued
+ *                or running.  A failed device call is reported here as
+ *                EDEVICE once its earlier results are drained.
+ * stream_info    host int64[8]: launches, results, output samples per ear,
+ *                submits refused with EAGAIN, largest launch (blocks),
+ *                generation buffers, samples per generation, blocks queued
+ *                but not launched.
+ * stream_close   renders what is queued, waits for the GPU and frees
+ *                everything; results not polled are dropped.  No other call
+ *                on the server may run during or after it.
+ * stream_submit, stream_end, stream_poll and stream_info may be called from
+ * several threads at once.  Times are CLOCK_MONOTONIC nanoseconds: submit,
+ * launch of the result's generation, and the moment the completion thread
+ * saw its output in host memory.
+ * ---------------------------------------------------------------------- */
+#define STREAM_DIRECT_LAUNCH 1
+#define STREAM_RESULT_TAIL 1
+
+typedef struct hrir_server hrir_server;
+
+typedef struct {
+    uint64_t tag;           /* as submitted */
+    int32_t stream_id;
+    int32_t n;              /* output samples per ear */
+    const float* out;       /* host f32[2][n], server owned, valid until the next poll */
+    int64_t t_submit_ns;
+    int64_t t_launch_ns;
+    int64_t t_done_ns;
+    int32_t flags;          /* STREAM_RESULT_TAIL for the result of stream_end */
+    int32_t pad;
+} hrir_result;
+
+int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t hbm_budget, int32_t flags, hrir_server** out);
+int stream_submit(hrir_server* server, int32_t stream_id, const float* host_block, int32_t n, int32_t filt_l,
+                  int32_t filt_r, uint64_t tag);
+int stream_end(hrir_server* server, int32_t stream_id, int32_t filt_l, int32_t filt_r, uint64_t tag);
+int stream_poll(hrir_server* server, hrir_result* out, int32_t max, int32_t timeout_us);
+int stream_info(const hrir_server* server, int64_t* info8);
+void stream_close(hrir_server* server);
+
+/* ------------------------------------------------------------------------
+ * Load generator for the streaming loop (a client of the stream_* calls
+ * above, for measurement).  Open loop: block arrivals form a Poisson process
+ * of rate_hz blocks/s over all streams for duration_s seconds; each arrival
+ * picks a stream uniformly in [0, n_streams), a length uniformly in
+ * [block_min, block_max] (<= 4096) and a block of that length at a random
+ * offset of the host signal; each stream keeps a random direction (filter
+ * pair 2d, 2d + 1 with d < n_filters / 2) that changes every ~16 blocks.
+ * A refused block (EAGAIN) is retried until admitted; its latency counts
+ * from its arrival time.  rate_hz <= 0 submits back to back for duration_s
+ * (the saturation rate).  At most max_blocks blocks are submitted.  A
+ * polling thread collects the results; the call returns when all are in,
+ * or with EDEVICE if none arrives for 30 s after submission ends.
+ * Latencies: arrival -> done (p50/p99/max) and submit -> done (p50/p99).
+ * The server must not be polled by anyone else meanwhile.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_streams;
+    int32_t block_min;
+    int32_t block_max;
+    int32_t n_filters;
+    double rate_hz;
+    double duration_s;
+    uint64_t seed;
+    int64_t max_blocks;
+    const float* signal;     /* host f32[signal_len] */
+    int64_t signal_len;
+} stream_load;
+
+typedef struct {
+    int64_t blocks;          /* blocks submitted (and rendered) */
+    int64_t out_samples;     /* output samples, both ears */
+    int64_t eagain;          /* refusals while admitting */
+    int64_t launches;        /* generations launched */
+    double offered_hz;       /* rate_hz, 0 for back to back */
+    double achieved_hz;      /* blocks / wall_s */
+    double out_samples_per_s;
+    double submit_s;         /* time spent submitting */
+    double wall_s;           /* first arrival to last result */
+    double mean_batch;       /* blocks per launch */
+    double p50_ms, p99_ms, max_ms;
+    double p50_server_ms, p99_server_ms;
+} stream_load_stats;
+
+int stream_loadgen(hrir_server* server, const stream_load* cfg, stream_load_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

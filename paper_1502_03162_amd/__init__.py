@@ -53,6 +53,33 @@ BLOCK_JOB_DTYPE = np.dtype([("stream_id", "<i4"), ("n", "<i4"), ("filt_l", "<i4"
 assert BLOCK_JOB_DTYPE.itemsize == ctypes.sizeof(BlockJob)
 
 
+STREAM_DIRECT_LAUNCH = 1
+STREAM_RESULT_TAIL = 1
+
+
+class HrirResult(ctypes.Structure):
+    _fields_ = [("tag", c_uint64), ("stream_id", c_int32), ("n", c_int32), ("out", POINTER(c_float)),
+                ("t_submit_ns", c_int64), ("t_launch_ns", c_int64), ("t_done_ns", c_int64), ("flags", c_int32),
+                ("pad", c_int32)]
+
+
+assert ctypes.sizeof(HrirResult) == 56
+
+
+class StreamLoad(ctypes.Structure):
+    _fields_ = [("n_streams", c_int32), ("block_min", c_int32), ("block_max", c_int32), ("n_filters", c_int32),
+                ("rate_hz", c_double), ("duration_s", c_double), ("seed", c_uint64), ("max_blocks", c_int64),
+                ("signal", POINTER(c_float)), ("signal_len", c_int64)]
+
+
+class StreamLoadStats(ctypes.Structure):
+    _fields_ = [("blocks", c_int64), ("out_samples", c_int64), ("eagain", c_int64), ("launches", c_int64),
+                ("offered_hz", c_double), ("achieved_hz", c_double), ("out_samples_per_s", c_double),
+                ("submit_s", c_double), ("wall_s", c_double), ("mean_batch", c_double), ("p50_ms", c_double),
+                ("p99_ms", c_double), ("max_ms", c_double), ("p50_server_ms", c_double),
+                ("p99_server_ms", c_double)]
+
+
 def _preload_torch_fft():
     """Load torch's hipFFT first (same soname as ROCm's), so the library's
     FFT leg runs on the FFT stack that matches torch's HIP runtime."""
@@ -101,6 +128,13 @@ def _load() -> ctypes.CDLL:
         "block_streams_destroy": (None, [c_void_p]),
         "spconv_autotune": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
                                     c_void_p, c_int64, c_void_p, c_char_p, c_int32, P_i32, P_i32, P_i32, P_d]),
+        "stream_open": (c_int, [c_void_p, c_int32, c_int64, c_int32, POINTER(c_void_p)]),
+        "stream_submit": (c_int, [c_void_p, c_int32, P_f, c_int32, c_int32, c_int32, c_uint64]),
+        "stream_end": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_uint64]),
+        "stream_poll": (c_int, [c_void_p, POINTER(HrirResult), c_int32, c_int32]),
+        "stream_info": (c_int, [c_void_p, P_i64]),
+        "stream_close": (None, [c_void_p]),
+        "stream_loadgen": (c_int, [c_void_p, POINTER(StreamLoad), POINTER(StreamLoadStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -115,7 +149,8 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_des
             "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
-            "block_streams_destroy")
+            "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
+            "stream_close", "stream_loadgen")
 
 
 def lib() -> ctypes.CDLL:
@@ -211,7 +246,11 @@ class Plan:
             _lib.spconv_plan_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
 
 
 def make_jobs(rows):
@@ -267,7 +306,11 @@ class Batch:
             _lib.spconv_batch_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
 
 
 def autotune(plan: Plan, src, src_off, src_len, jobs, out, cache_path=None, force_flags: int = 0,
@@ -326,7 +369,11 @@ class DensePlan:
             _lib.dense_plan_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
 
 
 class DenseBatch:
@@ -351,7 +398,11 @@ class DenseBatch:
             _lib.dense_batch_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
 
 
 # ---------------------------------------------------------------------------
@@ -390,7 +441,11 @@ class FftOla:
             _lib.fftola_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
 
 
 # ---------------------------------------------------------------------------
@@ -439,4 +494,85 @@ class Streams:
             _lib.block_streams_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
+
+
+class Server:
+    """Streaming request loop with continuous batching (stream_*).
+
+    submit/end return False when the server refuses the block for lack of
+    room (HRIR_EAGAIN): poll, then try again.  poll returns finished results
+    as (tag, stream_id, out, t_submit_ns, t_launch_ns, t_done_ns, is_tail)
+    with out a float32 array [2, n] (left, right) copied out of the server's
+    buffer."""
+
+    def __init__(self, plan: Plan, max_streams: int, hbm_budget: int = 256 << 20, flags: int = 0):
+        self.plan = plan
+        self.max_streams = max_streams
+        self.tail = plan.lf + plan.lg - 2
+        hd = c_void_p()
+        _check(_lib.stream_open(plan.handle, max_streams, int(hbm_budget), flags, byref(hd)))
+        self._h = hd
+        self._res = (HrirResult * 4096)()
+
+    def submit(self, stream_id: int, block, filt_l: int, filt_r: int, tag: int = 0) -> bool:
+        a = np.ascontiguousarray(block, dtype=np.float32)
+        rc = _lib.stream_submit(self._h, int(stream_id), _ptr(a, c_float), a.size, int(filt_l), int(filt_r), int(tag))
+        if rc == HRIR_EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def end(self, stream_id: int, filt_l: int, filt_r: int, tag: int = 0) -> bool:
+        rc = _lib.stream_end(self._h, int(stream_id), int(filt_l), int(filt_r), int(tag))
+        if rc == HRIR_EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_results: int = 4096, timeout_us: int = 0):
+        n = _lib.stream_poll(self._h, self._res, min(int(max_results), len(self._res)), int(timeout_us))
+        if n < 0:
+            _check(n)
+        out = []
+        for i in range(n):
+            r = self._res[i]
+            if r.n > 0:
+                y = np.ctypeslib.as_array(r.out, shape=(2 * r.n,)).reshape(2, r.n).copy()
+            else:
+                y = np.zeros((2, 0), dtype=np.float32)
+            out.append((int(r.tag), int(r.stream_id), y, int(r.t_submit_ns), int(r.t_launch_ns), int(r.t_done_ns),
+                        bool(r.flags & STREAM_RESULT_TAIL)))
+        return out
+
+    def info(self) -> dict:
+        v = np.zeros(8, dtype=np.int64)
+        _check(_lib.stream_info(self._h, _ptr(v, c_int64)))
+        keys = ("launches", "results", "samples", "eagain", "max_batch", "generations", "gen_samples", "queued")
+        return dict(zip(keys, (int(x) for x in v)))
+
+    def loadgen(self, signal, n_streams: int, rate_hz: float, duration_s: float, block_min: int = 64,
+                block_max: int = 1024, n_filters: int = 2, seed: int = 0, max_blocks: int = 1 << 22) -> dict:
+        """Runs the library's open-loop Poisson load generator (stream_loadgen)
+        against this server; rate_hz <= 0 submits back to back."""
+        sig = np.ascontiguousarray(signal, dtype=np.float32)
+        cfg = StreamLoad(int(n_streams), int(block_min), int(block_max), int(n_filters), float(rate_hz),
+                         float(duration_s), int(seed), int(max_blocks), _ptr(sig, c_float), sig.size)
+        st = StreamLoadStats()
+        _check(_lib.stream_loadgen(self._h, byref(cfg), byref(st)))
+        return {name: getattr(st, name) for name, _ in StreamLoadStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.stream_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass

@@ -17,68 +17,72 @@
 #include <type_traits>
 #include <vector>
 
-#include "hrir_internal.h"
+#include "block_internal.h"
 #include "render_common.h"
 
 namespace hrir {
 
-constexpr int kBlockMax = 4096;           // samples per block
-
-struct BJob {                             // device copy of block_job
-    int32_t slot, n, filt_l, filt_r, flush, pad;
-    int64_t in_off, out_off;
-};
-
+// One workgroup renders one job at a time; a persistent grid strides over
+// the job table (count read from device memory), a plain grid has one
+// workgroup per job.
 template <int LFP, int KP>
 __global__ __launch_bounds__(kThreads) void k_block(const float* __restrict__ in, const BJob* __restrict__ jobs,
+                                                    const int32_t* __restrict__ count, int n_jobs,
                                                     float* __restrict__ hist, int hist_stride,
                                                     const float* __restrict__ r, const int* __restrict__ P,
-                                                    const float* __restrict__ Gv, int kp, int k, int lf, int lg,
+                                                    const float* __restrict__ Gv, int kp, int lf, int lg,
                                                     float* __restrict__ out) {
     extern __shared__ float4 smem4[];
     float* s_ext = reinterpret_cast<float*>(smem4);                 // [LFP-1 + m]
-    const BJob j = jobs[blockIdx.x];
     const int H = lg - 1, HS = LFP - 1;
-    const int m = j.flush ? lf + lg - 2 : j.n;                      // samples in and out
-    float* z_ext = s_ext + round_up(HS + m, 4);                      // [H + m]
-    float* hs = hist + (int64_t)j.slot * hist_stride;               // s history then z history
-    float* hz = hs + HS;
     const int tid = threadIdx.x;
-    for (int i = tid; i < HS; i += kThreads) s_ext[i] = hs[i];
-    for (int i = tid; i < m; i += kThreads) s_ext[HS + i] = j.flush ? 0.0f : in[j.in_off + i];
-    for (int i = tid; i < H; i += kThreads) z_ext[i] = hz[i];
-    __syncthreads();
-    // z_ext[H + u] = sum_n r[n] s_ext[HS + u - n], n ascending (the offline order)
-    for (int u = tid; u < m; u += kThreads) {
-        float acc = 0.0f;
+    const int nj = count ? *count : n_jobs;
+    for (int ji = blockIdx.x; ji < nj; ji += gridDim.x) {
+        const BJob j = jobs[ji];
+        const bool flush = (j.flags & kJobFlush) != 0;
+        const int m = flush ? lf + lg - 2 : j.n;                    // samples in and out
+        float* z_ext = s_ext + round_up(HS + m, 4);                  // [H + m]
+        float* hs = hist + (int64_t)j.slot * hist_stride;           // s history then z history
+        float* hz = hs + HS;
+        for (int i = tid; i < HS; i += kThreads) s_ext[i] = hs[i];
+        for (int i = tid; i < m; i += kThreads) s_ext[HS + i] = flush ? 0.0f : in[j.in_off + i];
+        for (int i = tid; i < H; i += kThreads) z_ext[i] = hz[i];
+        __syncthreads();
+        // z_ext[H + u] = sum_n r[n] s_ext[HS + u - n], n ascending (the offline order)
+        for (int u = tid; u < m; u += kThreads) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int n = 0; n < LFP; ++n) acc = fmaf(r[n], s_ext[HS + u - n], acc);
-        z_ext[H + u] = acc;
-    }
-    __syncthreads();
-    // both ears; taps in slot order (padding taps beyond k have gain 0)
-    int pl[KP], pr[KP];
-    float gl[KP], gr[KP];
-#pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        pl[q] = P[(int64_t)j.filt_l * kp + q];
-        gl[q] = Gv[(int64_t)j.filt_l * kp + q];
-        pr[q] = P[(int64_t)j.filt_r * kp + q];
-        gr[q] = Gv[(int64_t)j.filt_r * kp + q];
-    }
-    for (int t = tid; t < m; t += kThreads) {
-        float al = 0.0f, ar = 0.0f;
+            for (int n = 0; n < LFP; ++n) acc = fmaf(r[n], s_ext[HS + u - n], acc);
+            z_ext[H + u] = acc;
+        }
+        __syncthreads();
+        // both ears; taps in slot order (padding taps beyond k have gain 0)
+        int pl[KP], pr[KP];
+        float gl[KP], gr[KP];
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-            al = fmaf(gl[q], z_ext[H + t - pl[q]], al);
-            ar = fmaf(gr[q], z_ext[H + t - pr[q]], ar);
+            pl[q] = P[(int64_t)j.filt_l * kp + q];
+            gl[q] = Gv[(int64_t)j.filt_l * kp + q];
+            pr[q] = P[(int64_t)j.filt_r * kp + q];
+            gr[q] = Gv[(int64_t)j.filt_r * kp + q];
         }
-        out[j.out_off + t] = al;
-        out[j.out_off + m + t] = ar;
+        for (int t = tid; t < m; t += kThreads) {
+            float al = 0.0f, ar = 0.0f;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+                al = fmaf(gl[q], z_ext[H + t - pl[q]], al);
+                ar = fmaf(gr[q], z_ext[H + t - pr[q]], ar);
+            }
+            out[j.out_off + t] = al;
+            out[j.out_off + m + t] = ar;
+        }
+        // new histories: the last HS samples of s_ext and H values of z_ext,
+        // or zeros when the stream ends here
+        const bool reset = (j.flags & kJobReset) != 0;
+        for (int i = tid; i < HS; i += kThreads) hs[i] = reset ? 0.0f : s_ext[m + i];
+        for (int i = tid; i < H; i += kThreads) hz[i] = reset ? 0.0f : z_ext[m + i];
+        __syncthreads();                                            // LDS is reused by the next job
     }
-    // new histories: the last HS samples of s_ext and H values of z_ext
-    for (int i = tid; i < HS; i += kThreads) hs[i] = s_ext[m + i];
-    for (int i = tid; i < H; i += kThreads) hz[i] = z_ext[m + i];
 }
 
 // Zero the histories of the listed slots (a fill kernel, so the call is safe
@@ -102,7 +106,7 @@ extern "C" int spconv_plan_device(const hrir_plan* plan, const float** r, const 
 struct hrir_streams {
     const hrir_plan* plan = nullptr;
     int lf = 0, lfp = 0, k = 0, kp = 0, lg = 0, n_filters = 0;
-    int max_streams = 0, hist_stride = 0, n_filt = 0;
+    int max_streams = 0, hist_stride = 0, n_filt = 0, device = 0;
     int call_id = 0;
     float* d_hist = nullptr;
     // job tables: pinned host staging, device copy (double buffered)
@@ -114,6 +118,47 @@ struct hrir_streams {
     int cap = 0, cur = 0;
     std::vector<int> seen;               // per-call uniqueness check
 };
+
+namespace hrir {
+
+BlockShape block_shape(const hrir_streams* s) {
+    return BlockShape{s->lf, s->lfp, s->k, s->kp, s->lg, s->n_filt, s->max_streams, s->hist_stride, s->device};
+}
+
+size_t block_lds_bytes(const BlockShape& sh, int max_m) {
+    return sizeof(float) * (size_t)(round_up(sh.lfp - 1 + max_m, 4) + sh.lg - 1 + max_m);
+}
+
+hipError_t block_enqueue(const hrir_streams* s, const float* d_in, const BJob* d_jobs, const int32_t* d_count,
+                         int n_jobs, int grid, int max_m, float* d_out, hipStream_t st) {
+    const float* dr;
+    const int* dp;
+    const float* dg;
+    int32_t lk[3];
+    if (spconv_plan_device(s->plan, &dr, &dp, &dg, lk) != HRIR_OK) return hipErrorInvalidValue;
+    const size_t lds = block_lds_bytes(block_shape(s), max_m);
+    bool launched = false;
+    auto go = [&](auto L, auto K) {
+        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        if (s->lfp == LV && s->kp == KV) {
+            hipLaunchKernelGGL((k_block<LV, KV>), dim3(grid), dim3(kThreads), lds, st, d_in, d_jobs, d_count, n_jobs,
+                               s->d_hist, s->hist_stride, dr, dp, dg, s->kp, s->lf, s->lg, d_out);
+            launched = true;
+        }
+    };
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    using K4 = std::integral_constant<int, 4>;
+    using K8 = std::integral_constant<int, 8>;
+    go(I16{}, K4{}); go(I16{}, K8{}); go(I16{}, I16{}); go(I16{}, I32{}); go(I16{}, I64{});
+    go(I32{}, K4{}); go(I32{}, K8{}); go(I32{}, I16{}); go(I32{}, I32{}); go(I32{}, I64{});
+    go(I64{}, K4{}); go(I64{}, K8{}); go(I64{}, I16{}); go(I64{}, I32{}); go(I64{}, I64{});
+    if (!launched) return hipErrorInvalidConfiguration;
+    return hipGetLastError();
+}
+
+}  // namespace hrir
 
 namespace {
 
@@ -151,6 +196,11 @@ extern "C" int block_streams_create(const hrir_plan* plan, int32_t max_streams, 
     s->plan = plan;
     s->lf = shp[0]; s->k = shp[1]; s->lg = shp[2]; s->lfp = lk[0]; s->kp = lk[1]; s->n_filt = lk[2];
     s->max_streams = max_streams;
+    hipError_t e0 = hipGetDevice(&s->device);
+    if (e0 != hipSuccess) {
+        delete s;
+        return fail(HRIR_EDEVICE, "block_streams_create: %s", hipGetErrorString(e0));
+    }
     s->hist_stride = round_up(s->lfp - 1 + s->lg - 1, 4);
     s->cap = max_streams;
     hipError_t e = hipMalloc(&s->d_hist, (size_t)max_streams * s->hist_stride * sizeof(float));
@@ -246,38 +296,14 @@ extern "C" int block_render(hrir_streams* s, const float* d_in, int64_t in_elems
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
     for (int i = 0; i < n_jobs; ++i) {
         const block_job& j = jobs[i];
-        s->h_jobs[b][i] = BJob{j.stream_id, j.n, j.filt_l, j.filt_r, (j.flags & BLOCK_FLUSH) ? 1 : 0, 0,
+        s->h_jobs[b][i] = BJob{j.stream_id, j.n, j.filt_l, j.filt_r, (j.flags & BLOCK_FLUSH) ? kJobFlush : 0, 0,
                                j.in_off, j.out_off};
     }
     e = hipMemcpyAsync(s->d_jobs[b], s->h_jobs[b], sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(s->used[b], st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
-    const float* dr;
-    const int* dp;
-    const float* dg;
-    int32_t lk[3];
-    (void)spconv_plan_device(s->plan, &dr, &dp, &dg, lk);
-    const size_t lds = sizeof(float) * (size_t)(round_up(s->lfp - 1 + max_m, 4) + s->lg - 1 + max_m);
     const float* din = d_in ? d_in : d_out;   // flush-only calls read no input
-    bool launched = false;
-    auto go = [&](auto L, auto K) {
-        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
-        if (s->lfp == LV && s->kp == KV) {
-            hipLaunchKernelGGL((k_block<LV, KV>), dim3(n_jobs), dim3(kThreads), lds, st, din, s->d_jobs[b], s->d_hist,
-                               s->hist_stride, dr, dp, dg, s->kp, s->k, s->lf, s->lg, d_out);
-            launched = true;
-        }
-    };
-    using I16 = std::integral_constant<int, 16>;
-    using I32 = std::integral_constant<int, 32>;
-    using I64 = std::integral_constant<int, 64>;
-    using K4 = std::integral_constant<int, 4>;
-    using K8 = std::integral_constant<int, 8>;
-    go(I16{}, K4{}); go(I16{}, K8{}); go(I16{}, I16{}); go(I16{}, I32{}); go(I16{}, I64{});
-    go(I32{}, K4{}); go(I32{}, K8{}); go(I32{}, I16{}); go(I32{}, I32{}); go(I32{}, I64{});
-    go(I64{}, K4{}); go(I64{}, K8{}); go(I64{}, I16{}); go(I64{}, I32{}); go(I64{}, I64{});
-    if (!launched) return fail(HRIR_EINVAL, "block_render: no kernel for lf pad %d, k pad %d", s->lfp, s->kp);
-    e = hipGetLastError();
+    e = block_enqueue(s, din, s->d_jobs[b], nullptr, n_jobs, n_jobs, max_m, d_out, st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
     return HRIR_OK;
 }

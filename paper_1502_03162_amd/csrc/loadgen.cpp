@@ -1,0 +1,152 @@
+// Open-loop load generator for the streaming request loop: Poisson block
+// arrivals over many streams, block lengths uniform in [block_min,
+// block_max], each stream at its own direction, changing now and then.  It
+// drives the loop only through the public stream_* calls (a client of the
+// library, like any serving front end) and reports throughput and the
+// arrival-to-done latency distribution.
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "hrir_internal.h"
+
+namespace {
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+double pct(std::vector<int64_t>& v, double q) {
+    if (v.empty()) return 0.0;
+    const size_t i = std::min(v.size() - 1, (size_t)std::floor(q * (double)(v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + (ptrdiff_t)i, v.end());
+    return (double)v[i] * 1e-6;
+}
+
+}  // namespace
+
+using hrir::fail;
+
+extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_load_stats* st) {
+    hrir::clear_error();
+    if (!srv || !cfg || !st || !cfg->signal) return fail(HRIR_EINVAL, "stream_loadgen: null pointer");
+    if (cfg->n_streams < 1 || cfg->block_min < 1 || cfg->block_max < cfg->block_min || cfg->block_max > 4096 ||
+        cfg->signal_len < cfg->block_max || cfg->n_filters < 2 || cfg->duration_s <= 0.0 || cfg->max_blocks < 1)
+        return fail(HRIR_EINVAL, "stream_loadgen: bad configuration");
+    int64_t info[8];
+    int rc = stream_info(srv, info);
+    if (rc) return rc;
+    const int64_t launches0 = info[0], eagain0 = info[3];
+    const int64_t cap = cfg->max_blocks;
+    std::vector<int64_t> arrival((size_t)cap), lat, lat_srv;
+    lat.reserve((size_t)cap);
+    lat_srv.reserve((size_t)cap);
+    std::atomic<int64_t> submitted{0};
+    std::atomic<bool> submit_done{false};
+    std::atomic<int64_t> give_up_ns{INT64_MAX};      // set once submission ends
+    std::atomic<int> poll_error{0};
+    int64_t out_samples = 0, n_done = 0, t_last_done = 0;
+
+    std::thread poller([&] {
+        std::vector<hrir_result> res(4096);
+        for (;;) {
+            const int n = stream_poll(srv, res.data(), (int32_t)res.size(), 1000);
+            if (n < 0) {
+                poll_error = n;
+                return;
+            }
+            for (int i = 0; i < n; ++i) {
+                const hrir_result& r = res[(size_t)i];
+                lat.push_back(r.t_done_ns - arrival[(size_t)r.tag]);
+                lat_srv.push_back(r.t_done_ns - r.t_submit_ns);
+                out_samples += 2 * (int64_t)r.n;
+                t_last_done = std::max(t_last_done, r.t_done_ns);
+            }
+            n_done += n;
+            if (submit_done && n_done >= submitted) return;
+            if (n == 0) {
+                if (now_ns() > give_up_ns) {          // results stopped coming: report, do not wait forever
+                    poll_error = HRIR_EDEVICE;
+                    return;
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+        }
+    });
+
+    std::mt19937_64 rng(cfg->seed);
+    std::uniform_int_distribution<int> len_d(cfg->block_min, cfg->block_max);
+    std::uniform_int_distribution<int> sid_d(0, cfg->n_streams - 1);
+    std::uniform_int_distribution<int> dir_d(0, cfg->n_filters / 2 - 1);
+    std::uniform_int_distribution<int64_t> off_d(0, cfg->signal_len - cfg->block_max);
+    std::exponential_distribution<double> gap_d(cfg->rate_hz > 0.0 ? cfg->rate_hz : 1.0);
+    std::vector<int> dir((size_t)cfg->n_streams);
+    for (int& d : dir) d = dir_d(rng);
+    const bool open_loop = cfg->rate_hz > 0.0;
+    const int64_t t0 = now_ns();
+    const int64_t t_stop = t0 + (int64_t)(cfg->duration_s * 1e9);
+    double t_next = (double)t0;
+    int64_t n = 0;
+    while (n < cap && poll_error == 0) {
+        int64_t t_arr;
+        if (open_loop) {
+            t_next += gap_d(rng) * 1e9;
+            t_arr = (int64_t)t_next;
+            if (t_arr >= t_stop) break;
+            for (int64_t t; (t = now_ns()) < t_arr;)
+                if (t_arr - t > 200000) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        } else {
+            t_arr = now_ns();
+            if (t_arr >= t_stop) break;
+        }
+        const int sid = sid_d(rng);
+        if ((rng() & 15) == 0) dir[(size_t)sid] = dir_d(rng);   // a direction change every ~16 blocks
+        const int len = len_d(rng);
+        const float* blk = cfg->signal + off_d(rng);
+        arrival[(size_t)n] = t_arr;
+        for (;;) {
+            rc = stream_submit(srv, sid, blk, len, 2 * dir[(size_t)sid], 2 * dir[(size_t)sid] + 1, (uint64_t)n);
+            if (rc != HRIR_EAGAIN) break;
+            std::this_thread::yield();
+        }
+        if (rc) break;
+        ++n;
+        submitted = n;
+    }
+    const int64_t t_sub_end = now_ns();
+    give_up_ns = t_sub_end + 30000000000LL;
+    submit_done = true;
+    poller.join();
+    if (rc) return rc;
+    if (poll_error)
+        return fail(poll_error, "stream_loadgen: %s", poll_error == HRIR_EDEVICE && n_done < submitted
+                                                          ? "results stopped arriving for 30 s"
+                                                          : "poll failed");
+    rc = stream_info(srv, info);
+    if (rc) return rc;
+    std::memset(st, 0, sizeof *st);
+    st->blocks = n;
+    st->out_samples = out_samples;
+    st->eagain = info[3] - eagain0;
+    st->launches = info[0] - launches0;
+    st->offered_hz = open_loop ? cfg->rate_hz : 0.0;
+    st->submit_s = (double)(t_sub_end - t0) * 1e-9;
+    st->wall_s = (double)(std::max(t_last_done, t_sub_end) - t0) * 1e-9;
+    st->achieved_hz = st->wall_s > 0 ? (double)n / st->wall_s : 0.0;
+    st->out_samples_per_s = st->wall_s > 0 ? (double)out_samples / st->wall_s : 0.0;
+    st->mean_batch = st->launches ? (double)n / (double)st->launches : 0.0;
+    st->p50_ms = pct(lat, 0.50);
+    st->p99_ms = pct(lat, 0.99);
+    st->max_ms = pct(lat, 1.0);
+    st->p50_server_ms = pct(lat_srv, 0.50);
+    st->p99_server_ms = pct(lat_srv, 0.99);
+    return HRIR_OK;
+}

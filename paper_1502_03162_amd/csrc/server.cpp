@@ -1,0 +1,494 @@
+// Streaming request loop with continuous batching over the block renderer
+// (Sec. IV-F: partitioned time-domain convolution, no added latency).
+//
+// Callers submit blocks of many streams at any time; the loop gathers what
+// has arrived into a generation (at most one block per stream, since a
+// stream's blocks must run in order through its history) and launches it as
+// soon as fewer than kDepth generations are on the device, so blocks that
+// arrive while others render join the next launch.  Generations live in a
+// ring of G buffers (pinned host staging + device memory, sized from the HBM
+// budget); a block is admitted into the oldest generation that can take it
+// and is refused with HRIR_EAGAIN when none of the G buffers can.
+//
+// Per generation, on one of two HIP streams (alternating):
+//   copy job table and inputs host -> device,
+//   wait for the previous generation's kernel (stream histories),
+//   block kernel (persistent grid from a HIP graph, or one workgroup per job),
+//   copy outputs device -> host pinned memory, record the done event.
+// Copies of one generation overlap the kernel of the other.  A completion
+// thread turns done events into results, handed out by stream_poll.
+#include <hip/hip_runtime.h>
+#include <time.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "block_internal.h"
+
+using namespace hrir;
+
+namespace {
+
+constexpr int kDepth = 2;          // generations on the device at once
+constexpr int kMaxGens = 8;
+constexpr int kPersistentGrid = 1024;
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+enum GenState { kFree, kOpen, kLaunched, kDone, kHanded };
+
+struct Gen {
+    int64_t seq = -1;
+    GenState state = kFree;
+    int n_jobs = 0, max_m = 0, remaining = 0;
+    bool failed = false;                   // its launch failed: no results
+    int64_t in_used = 0, out_used = 0;     // input floats; output samples per ear
+    int64_t t_launch = 0, t_done = 0;
+    // pinned host: h_hdr[0] = job count, then the job table; inputs; outputs
+    int32_t* h_hdr = nullptr;
+    BJob* h_jobs = nullptr;
+    float* h_in = nullptr;
+    float* h_out = nullptr;
+    // device mirror
+    int32_t* d_hdr = nullptr;
+    BJob* d_jobs = nullptr;
+    float* d_in = nullptr;
+    float* d_out = nullptr;
+    hipEvent_t ev_kernel = nullptr, ev_done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> tag;
+    std::vector<int64_t> t_submit;
+};
+
+}  // namespace
+
+struct hrir_server {
+    hrir_streams* streams = nullptr;
+    BlockShape sh{};
+    int flags = 0;
+    int cap_jobs = 0, n_gens = 0;
+    int64_t cap_samples = 0;
+    int tail = 0;
+    hipStream_t st[2] = {nullptr, nullptr};
+    std::vector<Gen> gens;
+    std::vector<int64_t> last_seq;          // per stream: generation of its newest block
+
+    std::mutex mu;
+    std::condition_variable cv_work;        // dispatcher: new jobs, a free device slot, close
+    std::condition_variable cv_done;        // completer: a launch; pollers: results
+    int64_t head = 0;                       // oldest generation not yet free
+    int64_t tail_seq = 0;                   // one past the newest opened generation
+    int64_t next_launch = 0, next_done = 0;
+    int64_t enqueued = 0;                   // generations whose device work is fully enqueued
+    std::deque<hrir_result> results;
+    std::deque<int64_t> result_gen;         // generation of each queued result
+    bool closing = false, dispatcher_exited = false;
+    int err_code = 0;
+    std::string err_msg;
+    // statistics
+    int64_t n_launches = 0, n_results = 0, n_samples = 0, n_eagain = 0, max_batch = 0;
+
+    std::thread dispatcher, completer;
+
+    Gen& gen(int64_t seq) { return gens[(size_t)(seq % n_gens)]; }
+};
+
+namespace {
+
+void set_error(hrir_server* s, const char* where, hipError_t e) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->err_code) {
+        s->err_code = HRIR_EDEVICE;
+        s->err_msg = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+}
+
+// Opens generation `seq` (its buffer is free) for submissions.  Lock held.
+void open_gen(hrir_server* s, int64_t seq) {
+    Gen& g = s->gen(seq);
+    g.seq = seq;
+    g.state = kOpen;
+    g.n_jobs = 0;
+    g.max_m = 0;
+    g.in_used = 0;
+    g.out_used = 0;
+    g.remaining = 0;
+    g.failed = false;
+    g.tag.clear();
+    g.t_submit.clear();
+}
+
+// Releases generations whose results have all been handed out, in order.
+void release_handed(hrir_server* s) {
+    while (s->head < s->tail_seq && s->gen(s->head).state == kHanded) {
+        s->gen(s->head).state = kFree;
+        ++s->head;
+    }
+}
+
+// Places one job (block or flush) for `stream` in the oldest generation that
+// can take it.  Lock held.  Returns the generation or -1 (no room: EAGAIN).
+int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
+    int64_t q = std::max(s->next_launch, s->last_seq[stream] + 1);
+    for (;; ++q) {
+        if (q >= s->head + s->n_gens) return -1;
+        if (q == s->tail_seq) {
+            if (s->gen(q).state != kFree) return -1;
+            open_gen(s, q);
+            ++s->tail_seq;
+        }
+        Gen& g = s->gen(q);
+        if (g.n_jobs < s->cap_jobs && g.in_used + n_in <= s->cap_samples && g.out_used + m <= s->cap_samples)
+            return q;
+    }
+}
+
+int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, int32_t filt_l, int32_t filt_r,
+                uint64_t tag, bool end, const char* fn) {
+    const int m = end ? s->tail : n;
+    const int64_t n_in = end ? 0 : n;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
+    if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
+    const int64_t q = place(s, stream, m, n_in);
+    if (q < 0) {
+        ++s->n_eagain;
+        return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+    }
+    Gen& g = s->gen(q);
+    const int i = g.n_jobs++;
+    g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, g.in_used,
+                       2 * g.out_used};
+    if (n_in) std::memcpy(g.h_in + g.in_used, block, sizeof(float) * (size_t)n_in);
+    g.in_used += n_in;
+    g.out_used += m;
+    g.max_m = std::max(g.max_m, m);
+    g.tag.push_back(tag);
+    g.t_submit.push_back(now_ns());
+    s->last_seq[stream] = q;
+    s->cv_work.notify_all();
+    return HRIR_OK;
+}
+
+// Enqueues generation g on HIP stream `st`; `prev` is the previous
+// generation's kernel event (null for the first).
+hipError_t launch_gen(hrir_server* s, Gen& g, hipStream_t st, hipEvent_t prev) {
+    *g.h_hdr = g.n_jobs;
+    hipError_t e = hipMemcpyAsync(g.d_hdr, g.h_hdr, 64 + sizeof(BJob) * (size_t)g.n_jobs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g.in_used)
+        e = hipMemcpyAsync(g.d_in, g.h_in, sizeof(float) * (size_t)g.in_used, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && prev) e = hipStreamWaitEvent(st, prev, 0);
+    if (e == hipSuccess) {
+        if (g.exec)
+            e = hipGraphLaunch(g.exec, st);
+        else
+            e = block_enqueue(s->streams, g.d_in, g.d_jobs, nullptr, g.n_jobs, g.n_jobs, g.max_m, g.d_out, st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(g.ev_kernel, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g.h_out, g.d_out, sizeof(float) * 2 * (size_t)g.out_used, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(g.ev_done, st);
+    return e;
+}
+
+void dispatcher_main(hrir_server* s) {
+    (void)hipSetDevice(s->sh.device);
+    hipEvent_t prev = nullptr;
+    for (;;) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_work.wait(lk, [&] {
+            if (s->err_code) return true;
+            const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
+            if (s->closing && !ready) return true;
+            return ready && s->next_launch - s->next_done < kDepth;
+        });
+        const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
+        if (s->err_code || (s->closing && !ready)) {
+            s->dispatcher_exited = true;
+            s->cv_done.notify_all();
+            return;
+        }
+        const int64_t seq = s->next_launch++;
+        Gen& g = s->gen(seq);
+        g.state = kLaunched;
+        g.t_launch = now_ns();
+        s->n_launches++;
+        s->max_batch = std::max<int64_t>(s->max_batch, g.n_jobs);
+        lk.unlock();
+        // the generation no longer takes submissions: its tables are stable
+        const hipError_t e = launch_gen(s, g, s->st[seq & 1], prev);
+        prev = g.ev_kernel;
+        if (e != hipSuccess) {
+            set_error(s, "stream loop launch", e);
+            std::lock_guard<std::mutex> lk2(s->mu);
+            g.failed = true;
+            s->enqueued = seq + 1;
+            s->dispatcher_exited = true;
+            s->cv_done.notify_all();
+            return;
+        }
+        // only now is the done event recorded for this generation: before
+        // this, querying it would see an earlier use of the buffer
+        lk.lock();
+        s->enqueued = seq + 1;
+        s->cv_done.notify_all();
+    }
+}
+
+void completer_main(hrir_server* s) {
+    (void)hipSetDevice(s->sh.device);
+    for (;;) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] { return s->next_done < s->enqueued || s->dispatcher_exited || s->err_code; });
+        if (s->next_done >= s->enqueued) {
+            if (s->dispatcher_exited || s->err_code) return;
+            continue;
+        }
+        const int64_t seq = s->next_done;
+        Gen& g = s->gen(seq);
+        const bool failed = g.failed;
+        lk.unlock();
+        hipError_t e = hipSuccess;
+        if (!failed)
+            while ((e = hipEventQuery(g.ev_done)) == hipErrorNotReady) std::this_thread::yield();
+        const int64_t t_done = now_ns();
+        if (e != hipSuccess) {
+            set_error(s, "stream loop completion", e);
+            return;
+        }
+        lk.lock();
+        g.t_done = t_done;
+        g.state = kDone;
+        g.remaining = failed ? 0 : g.n_jobs;
+        if (failed) g.state = kHanded;
+        for (int i = 0; i < g.remaining; ++i) {
+            const BJob& j = g.h_jobs[i];
+            const int m = block_job_len(s->sh, j);
+            hrir_result r{};
+            r.tag = g.tag[i];
+            r.stream_id = j.slot;
+            r.n = m;
+            r.out = g.h_out + j.out_off;
+            r.t_submit_ns = g.t_submit[i];
+            r.t_launch_ns = g.t_launch;
+            r.t_done_ns = t_done;
+            r.flags = (j.flags & kJobFlush) ? STREAM_RESULT_TAIL : 0;
+            s->results.push_back(r);
+            s->result_gen.push_back(seq);
+            s->n_samples += m;
+        }
+        s->n_results += g.remaining;
+        ++s->next_done;
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+}
+
+void free_server(hrir_server* s) {
+    for (Gen& g : s->gens) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        if (g.ev_kernel) (void)hipEventDestroy(g.ev_kernel);
+        if (g.ev_done) (void)hipEventDestroy(g.ev_done);
+        (void)hipHostFree(g.h_hdr);
+        (void)hipHostFree(g.h_in);
+        (void)hipHostFree(g.h_out);
+        (void)hipFree(g.d_hdr);
+        (void)hipFree(g.d_in);
+        (void)hipFree(g.d_out);
+    }
+    for (hipStream_t& x : s->st)
+        if (x) (void)hipStreamDestroy(x);
+    if (s->streams) block_streams_destroy(s->streams);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t hbm_budget, int32_t flags,
+                           hrir_server** out) {
+    clear_error();
+    if (!plan || !out) return fail(HRIR_EINVAL, "stream_open: null pointer");
+    *out = nullptr;
+    if (max_streams < 1 || max_streams > (1 << 20))
+        return fail(HRIR_EINVAL, "stream_open: max_streams=%d outside [1, 2^20]", max_streams);
+    if (flags & ~STREAM_DIRECT_LAUNCH) return fail(HRIR_EINVAL, "stream_open: unknown flags 0x%x", flags);
+    int32_t shp[3];
+    int rc = spconv_plan_shape(plan, shp);
+    if (rc) return rc;
+    const int lf = shp[0], lg = shp[2];
+    const int tail = lf + lg - 2;
+    const int64_t min_cap = std::max(kBlockMax, tail);
+    auto* s = new (std::nothrow) hrir_server;
+    if (!s) return fail(HRIR_ENOMEM, "stream_open: out of host memory");
+    rc = block_streams_create(plan, max_streams, &s->streams);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    s->sh = block_shape(s->streams);
+    // device bytes: histories, then per generation a header + job table,
+    // inputs (4 B per sample) and two output ears (8 B per sample)
+    const int64_t hist_bytes = (int64_t)max_streams * s->sh.hist_stride * 4;
+    const int64_t fixed = 64 + 32LL * max_streams;
+    auto per_gen = [&](int64_t cap) { return fixed + 12 * cap; };
+    const int64_t avail = hbm_budget - hist_bytes;
+    int64_t cap = std::max<int64_t>(min_cap, (int64_t)max_streams * 1024);
+    int64_t n_gens = avail > 0 ? avail / per_gen(cap) : 0;
+    if (n_gens > kMaxGens) n_gens = kMaxGens;
+    for (int G = 3; n_gens < 3 && G >= 2; --G) {
+        cap = (avail / G - fixed) / 12 / 64 * 64;
+        if (cap >= min_cap) {
+            n_gens = G;
+            break;
+        }
+    }
+    if (n_gens < 2 || cap < min_cap) {
+        free_server(s);
+        return fail(HRIR_EINVAL, "stream_open: hbm_budget %lld too small; at least %lld bytes are needed",
+                    (long long)hbm_budget, (long long)(hist_bytes + 2 * per_gen(min_cap)));
+    }
+
+    s->flags = flags;
+    s->cap_jobs = max_streams;
+    s->cap_samples = cap;
+    s->n_gens = (int)n_gens;
+    s->tail = tail;
+    s->last_seq.assign(max_streams, -1);
+    s->gens.resize(s->n_gens);
+    hipError_t e = hipSuccess;
+    for (hipStream_t& x : s->st)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+    const size_t hdr_bytes = 64 + sizeof(BJob) * (size_t)s->cap_jobs;
+    const int max_m = (int)min_cap;
+    for (Gen& g : s->gens) {
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_hdr, hdr_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_in, sizeof(float) * (size_t)cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_out, sizeof(float) * 2 * (size_t)cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&g.d_hdr, hdr_bytes);
+        if (e == hipSuccess) e = hipMalloc((void**)&g.d_in, sizeof(float) * (size_t)cap);
+        if (e == hipSuccess) e = hipMalloc((void**)&g.d_out, sizeof(float) * 2 * (size_t)cap);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_kernel, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_done, hipEventDisableTiming);
+        if (e != hipSuccess) break;
+        g.h_jobs = reinterpret_cast<BJob*>(reinterpret_cast<char*>(g.h_hdr) + 64);
+        g.d_jobs = reinterpret_cast<BJob*>(reinterpret_cast<char*>(g.d_hdr) + 64);
+        if (!(flags & STREAM_DIRECT_LAUNCH)) {
+            // persistent grid over the job table, count read from the header;
+            // LDS sized for the longest job, so one graph serves every batch
+            const int grid = std::min(kPersistentGrid, s->cap_jobs);
+            e = hipStreamBeginCapture(s->st[0], hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el =
+                    block_enqueue(s->streams, g.d_in, g.d_jobs, g.d_hdr, 0, grid, max_m, g.d_out, s->st[0]);
+                e = hipStreamEndCapture(s->st[0], &g.graph);
+                if (e == hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) break;
+        }
+    }
+    if (e != hipSuccess) {
+        free_server(s);
+        return fail(e == hipErrorOutOfMemory ? HRIR_ENOMEM : HRIR_EDEVICE, "stream_open: %s", hipGetErrorString(e));
+    }
+    s->dispatcher = std::thread(dispatcher_main, s);
+    s->completer = std::thread(completer_main, s);
+    *out = s;
+    return HRIR_OK;
+}
+
+extern "C" int stream_submit(hrir_server* s, int32_t stream_id, const float* host_block, int32_t n, int32_t filt_l,
+                             int32_t filt_r, uint64_t tag) {
+    clear_error();
+    if (!s || !host_block) return fail(HRIR_EINVAL, "stream_submit: null pointer");
+    if (stream_id < 0 || stream_id >= s->cap_jobs)
+        return fail(HRIR_EINVAL, "stream_submit: stream %d outside [0, %d)", stream_id, s->cap_jobs);
+    if (n < 1 || n > kBlockMax) return fail(HRIR_EINVAL, "stream_submit: n=%d outside [1, %d]", n, kBlockMax);
+    if (filt_l < 0 || filt_l >= s->sh.n_filt || filt_r < 0 || filt_r >= s->sh.n_filt)
+        return fail(HRIR_EINVAL, "stream_submit: filter (%d, %d) outside [0, %d)", filt_l, filt_r, s->sh.n_filt);
+    return enqueue_job(s, stream_id, host_block, n, filt_l, filt_r, tag, false, "stream_submit");
+}
+
+extern "C" int stream_end(hrir_server* s, int32_t stream_id, int32_t filt_l, int32_t filt_r, uint64_t tag) {
+    clear_error();
+    if (!s) return fail(HRIR_EINVAL, "stream_end: null pointer");
+    if (stream_id < 0 || stream_id >= s->cap_jobs)
+        return fail(HRIR_EINVAL, "stream_end: stream %d outside [0, %d)", stream_id, s->cap_jobs);
+    if (filt_l < 0 || filt_l >= s->sh.n_filt || filt_r < 0 || filt_r >= s->sh.n_filt)
+        return fail(HRIR_EINVAL, "stream_end: filter (%d, %d) outside [0, %d)", filt_l, filt_r, s->sh.n_filt);
+    return enqueue_job(s, stream_id, nullptr, 0, filt_l, filt_r, tag, true, "stream_end");
+}
+
+extern "C" int stream_poll(hrir_server* s, hrir_result* out, int32_t max, int32_t timeout_us) {
+    clear_error();
+    if (!s || (max > 0 && !out)) return fail(HRIR_EINVAL, "stream_poll: null pointer");
+    if (max < 0) return fail(HRIR_EINVAL, "stream_poll: max=%d < 0", max);
+    std::unique_lock<std::mutex> lk(s->mu);
+    // results handed out by the previous poll are no longer referenced
+    release_handed(s);
+    s->cv_work.notify_all();
+    // wake on results or an error; never wait when nothing is queued or running
+    auto pending = [&] { return !s->results.empty() || s->err_code || s->next_done == s->tail_seq; };
+    if (timeout_us < 0)
+        s->cv_done.wait(lk, pending);
+    else if (timeout_us > 0)
+        s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), pending);
+    if (s->results.empty() && s->err_code) return fail(s->err_code, "stream_poll: %s", s->err_msg.c_str());
+    int n = 0;
+    while (n < max && !s->results.empty()) {
+        out[n++] = s->results.front();
+        const int64_t seq = s->result_gen.front();
+        s->results.pop_front();
+        s->result_gen.pop_front();
+        Gen& g = s->gen(seq);
+        if (--g.remaining == 0) g.state = kHanded;
+    }
+    return n;
+}
+
+extern "C" int stream_info(const hrir_server* s, int64_t* info8) {
+    clear_error();
+    if (!s || !info8) return fail(HRIR_EINVAL, "stream_info: null pointer");
+    auto* m = const_cast<hrir_server*>(s);
+    std::lock_guard<std::mutex> lk(m->mu);
+    int64_t queued = 0;
+    for (int64_t q = s->next_launch; q < s->tail_seq; ++q) queued += m->gen(q).n_jobs;
+    info8[0] = s->n_launches;
+    info8[1] = s->n_results;
+    info8[2] = s->n_samples;
+    info8[3] = s->n_eagain;
+    info8[4] = s->max_batch;
+    info8[5] = s->n_gens;
+    info8[6] = s->cap_samples;
+    info8[7] = queued;
+    return HRIR_OK;
+}
+
+extern "C" void stream_close(hrir_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->closing = true;
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    if (s->completer.joinable()) s->completer.join();
+    for (hipStream_t x : s->st)
+        if (x) (void)hipStreamSynchronize(x);
+    free_server(s);
+}

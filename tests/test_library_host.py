@@ -112,3 +112,45 @@ def test_plan_argument_errors_before_any_device_call():
         with pytest.raises(H.HrirError) as e:
             H.Plan(*args)
         assert e.value.code == H.HRIR_EINVAL and msg in str(e.value)
+
+
+def test_stream_calls_reject_null_handles():
+    lib = H.lib()
+    hd = ctypes.c_void_p()
+    assert lib.stream_open(None, 4, 1 << 24, 0, ctypes.byref(hd)) == H.HRIR_EINVAL
+    assert lib.stream_submit(None, 0, None, 1, 0, 1, 0) == H.HRIR_EINVAL
+    assert lib.stream_end(None, 0, 0, 1, 0) == H.HRIR_EINVAL
+    assert lib.stream_poll(None, None, 0, 0) == H.HRIR_EINVAL
+    assert lib.stream_info(None, None) == H.HRIR_EINVAL
+    assert lib.stream_loadgen(None, None, None) == H.HRIR_EINVAL
+    lib.stream_close(None)                              # no-op
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof/offsetof of every struct of the ABI, from a C program compiled
+    against the header, equal the binding's ctypes layouts."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"spconv_job": H.SpconvJob, "block_job": H.BlockJob, "hrir_result": H.HrirResult,
+               "stream_load": H.StreamLoad, "stream_load_stats": H.StreamLoadStats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hrir.h"', "int main(void) {"]
+    for name, ct in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in ct._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for name, ct in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(ct), name
+        for field, _ in ct._fields_:
+            assert got[(name, field)] == getattr(ct, field).offset, (name, field)
