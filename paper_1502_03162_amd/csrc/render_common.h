@@ -71,7 +71,7 @@ __host__ __device__ inline int lds_z_len(int TB, int lg) { return round_up(TB + 
 // Stage s_win[i] = s[t0 - H - (LFP-1) + i] for i < nz8 + LFP + 4 in LDS (zero
 // outside the signal), enough for z_win[u] = z[t0 - H + u], u < nz8 (a
 // multiple of 8).  Ends with a barrier.
-template <int LFP>
+template <int LFP, int NT = kThreads>
 __device__ __forceinline__ void stage_s(const TileDesc& td, const float* __restrict__ src, int H, int nz8,
                                         float* s_win) {
     const int tid = threadIdx.x;
@@ -84,23 +84,23 @@ __device__ __forceinline__ void stage_s(const TileDesc& td, const float* __restr
     const int ns4 = ns / 4;
     if (sbase >= 0 && sbase + ns <= td.src_len) {
         // interior tile (the tile-uniform common case): no per-element tests
-        for (int b4 = 0; b4 < ns4; b4 += kThreads * kStageV) {
+        for (int b4 = 0; b4 < ns4; b4 += NT * kStageV) {
             float4 v[kStageV];
 #pragma unroll
             for (int u = 0; u < kStageV; ++u) {
-                const int i4 = min(b4 + u * kThreads + tid, ns4 - 1);
+                const int i4 = min(b4 + u * NT + tid, ns4 - 1);
                 const f4u x = *reinterpret_cast<const f4u*>(sp + sbase + 4 * i4);
                 v[u] = make_float4(x.x, x.y, x.z, x.w);
             }
 #pragma unroll
             for (int u = 0; u < kStageV; ++u) {
-                const int i4 = b4 + u * kThreads + tid;
+                const int i4 = b4 + u * NT + tid;
                 if (i4 < ns4) *reinterpret_cast<float4*>(s_win + 4 * i4) = v[u];
             }
         }
     } else {
         // tile overlapping either end of the source: zero outside [0, src_len)
-        for (int i = tid; i < ns; i += kThreads) {
+        for (int i = tid; i < ns; i += NT) {
             const int64_t q = sbase + i;
             s_win[i] = (q >= 0 && q < td.src_len) ? sp[q] : 0.0f;
         }

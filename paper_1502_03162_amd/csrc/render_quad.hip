@@ -1,9 +1,9 @@
 // Quad LDS-gather sparse render kernel for gfx950 (the default render path).
 //
 // Same tiling as the other fused kernels (one source, TB outputs, a group of
-// that source's (direction, ear) jobs per 256-thread workgroup; z formed in
-// LDS by the resonance FIR and shared by every job of the tile), but the z
-// tile is kept as four copies shifted by 0..3 samples:
+// that source's (direction, ear) jobs per workgroup; z formed in LDS by the
+// resonance FIR and shared by every job of the tile), but the z tile is kept
+// as four copies shifted by 0..3 samples:
 //     Zc[m] = z[t0 - H + m + c],   c = 0..3.
 // Lane l of a wave owns outputs q = c0 + 4 l + 256 j + i (i < 4, j < 4) of
 // a 1024-output chunk.  For a tap at position p the four outputs of a quad
@@ -15,6 +15,11 @@
 //
 // The FIR keeps its z values in registers across a barrier, so the copies
 // can overwrite the staged source: LDS per tile is 4 (TB + H) floats.
+//
+// Workgroups have 8 waves: with 4 tiles resident per CU (LDS-bound at
+// TB = 2048) that is 32 waves per CU, enough outstanding stores and LDS reads
+// to keep both pipes busy while some waves wait on the source reads of a new
+// tile, which queue behind the output writes in HBM.
 //
 // Summation order per output: FIR taps 0..lf-1, then kept taps 0..K-1, one
 // fma each into one accumulator -- the order of every other kernel, so the
@@ -28,8 +33,11 @@ namespace hrir {
 
 constexpr int kQR = 16;               // outputs per lane per chunk (4 quads)
 constexpr int kQChunk = 64 * kQR;     // outputs per wave per chunk
-constexpr int kQMaxPass = 4;          // FIR passes of 8 z values per thread
+constexpr int kQThreads = 512;        // 8 wave64 per workgroup
+constexpr int kQWaves = kQThreads / 64;
+constexpr int kQPass = 2;             // FIR passes of 8 z values per thread (8192 z: tiles up to 4096)
 static_assert(kQChunk == 1024, "quad chunk");
+static_assert(kQPass * kQThreads * kZpt >= kQuadTileMax + 2048 + 3, "FIR passes cover the largest tile");
 
 // Floats per shifted copy: holds m < TB + H (+ padding so that the copies
 // start on different banks).
@@ -55,16 +63,16 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
     float* s_win = lds;
     float* zc = lds;                           // the copies overwrite s_win after the FIR
 
-    stage_s<LFP>(td, src, H, nz8, s_win);
+    stage_s<LFP, kQThreads>(td, src, H, nz8, s_win);
 
     // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)
     float rr[LFP];
 #pragma unroll
     for (int n = 0; n < LFP; ++n) rr[n] = r[n];
-    float zz[kQMaxPass][kZpt];
+    float zz[kQPass][kZpt];
 #pragma unroll
-    for (int ps = 0; ps < kQMaxPass; ++ps) {
-        const int u0 = (ps * kThreads + tid) * kZpt;
+    for (int ps = 0; ps < kQPass; ++ps) {
+        const int u0 = (ps * kQThreads + tid) * kZpt;
         if (u0 < nz8) {
             float w[LFP + kZpt];
 #pragma unroll
@@ -85,8 +93,8 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
     // Zc[m] = z_win[m + c] for m < TB + H; interior groups of 8 without tests
     const int mlim = TB + H;
 #pragma unroll
-    for (int ps = 0; ps < kQMaxPass; ++ps) {
-        const int u0 = (ps * kThreads + tid) * kZpt;
+    for (int ps = 0; ps < kQPass; ++ps) {
+        const int u0 = (ps * kQThreads + tid) * kZpt;
         if (u0 >= 4 && u0 + kZpt <= mlim) {
             float* z0 = zc + u0;
             *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);
@@ -172,14 +180,17 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
                     }
             }
     };
-    if (td.job_count >= kWaves) {
-        for (int q = wave; q < td.job_count; q += kWaves) {
+    if (td.job_count >= kQWaves) {
+        for (int q = wave; q < td.job_count; q += kQWaves) {
             const JobDesc jd = jobs[td.job_begin + q];
             load_taps(jd);
+            // one chunk body in the loop: unrolling it doubles the hot code
+#pragma unroll 1
             for (int ch = 0; ch < nchunk; ++ch) render_chunk(jd, ch);
         }
     } else {
-        for (int it = wave; it < td.job_count * nchunk; it += kWaves) {
+#pragma unroll 1
+        for (int it = wave; it < td.job_count * nchunk; it += kQWaves) {
             const int q = it / nchunk;
             const JobDesc jd = jobs[td.job_begin + q];
             load_taps(jd);
@@ -189,7 +200,7 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
 }
 
 template <int LFP, int KP>
-__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_quad(const float* __restrict__ src,
+__global__ __launch_bounds__(kQThreads, 4) void k_render_quad(const float* __restrict__ src,
                                                                      const TileDesc* __restrict__ tiles,
                                                                      const JobDesc* __restrict__ jobs,
                                                                      const float* __restrict__ r,
@@ -203,7 +214,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_render_quad(const float
 
 // Persistent variant over the device tile counter (see k_render_persistent).
 template <int LFP, int KP>
-__global__ __launch_bounds__(kThreads, kMinWaves) void k_render_quad_persistent(
+__global__ __launch_bounds__(kQThreads, 4) void k_render_quad_persistent(
     const float* __restrict__ src, const TileDesc* __restrict__ tiles, int n_tiles,
     const JobDesc* __restrict__ jobs, const float* __restrict__ r, const int* __restrict__ P,
     const float* __restrict__ Gv, float* __restrict__ out, int lg, int TB, int* __restrict__ ctr) {
@@ -256,7 +267,7 @@ int quad_prepare(int lfp, int kp, size_t lds_bytes, bool persistent, int64_t n_t
             return HRIR_OK;
         }
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, kThreads, lds_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, kQThreads, lds_bytes);
         if (e == hipSuccess) e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
@@ -271,10 +282,10 @@ int quad_launch(int lfp, int kp, bool persistent, int grid, size_t lds_bytes, hi
     return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
         constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
         if (persistent)
-            hipLaunchKernelGGL((k_render_quad_persistent<LV, KV>), dim3(grid), dim3(kThreads), lds_bytes, st, src,
+            hipLaunchKernelGGL((k_render_quad_persistent<LV, KV>), dim3(grid), dim3(kQThreads), lds_bytes, st, src,
                                tiles, n_tiles, jobs, r, P, Gv, out, lg, TB, ctr);
         else
-            hipLaunchKernelGGL((k_render_quad<LV, KV>), dim3((unsigned)n_tiles), dim3(kThreads), lds_bytes, st, src,
+            hipLaunchKernelGGL((k_render_quad<LV, KV>), dim3((unsigned)n_tiles), dim3(kQThreads), lds_bytes, st, src,
                                tiles, jobs, r, P, Gv, out, lg, TB);
         return HRIR_OK;
     });
