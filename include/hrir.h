@@ -83,6 +83,57 @@ int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf, int32_t it
                    int32_t* nnz_out, double* err_db_out, double* cost_out);
 
 /* ------------------------------------------------------------------------
+ * The paper's sparsifier (Sec. III-D): with the resonance filter f fixed,
+ * each reflection filter solves the penalised L1-NNLS problem of Eq. (14),
+ *     min_g ||D (f * g - x)||^2 + lambda sum(g),  g >= 0,
+ * for a residual transform D, and entries <= threshold (1e-4 in the paper)
+ * are discarded.  Host only, FP64, synchronous; rows run in parallel and the
+ * results do not depend on the thread count.
+ *
+ * Transforms: HRIR_D_IDENTITY; HRIR_D_CONV, the Toeplitz matrix of the
+ * Gaussian N_sigma(k) = exp(-k^2 / 2 sigma^2) / (sigma sqrt(2 pi)) (Eq. (15));
+ * HRIR_D_WINDOW, diag(exp(-t^2 / sigma^2)), t = 0..m-1 (Eq. (16); sigma =
+ * +inf is the identity).
+ *
+ * hrir_sparsify
+ *   X, n, m      host f64[n][m], one HRIR per row (m = lf + lg - 1).
+ *   f, lf        host f64[lf], the fixed resonance filter.
+ *   sigma        host f64[n] per-row bandwidth (null for HRIR_D_IDENTITY).
+ *   lambda       host f64[n] per-row L1 weight, or null: then each row's
+ *                lambda is the smallest found by 50 steps of geometric
+ *                bisection on [1e-12, 1] * lambda_max (lambda_max = 2 max
+ *                A^T D x, where g = 0 becomes optimal) whose solution keeps
+ *                at most target_nnze entries; 0 if lambda = 0 already does.
+ *   threshold    discard level (>= 0).
+ *   k            output slots per row: the kept entries in ascending position
+ *                order, padded with (p = 0, g = 0); a row with more than k
+ *                entries keeps its k largest (ties to the lower position).
+ *   p_out, g_out host i32[n][k], f32[n][k] (a tap table for spconv_plan).
+ *   nnze_out     host i32[n] or null: entries kept before the k-slot cut.
+ *   lambda_out   host f64[n] or null: the lambda used.
+ *   err_db_out   host f64[n] or null: 10 log10(||x - f * g||^2 / ||x||^2)
+ *                of the k-slot filter.
+ * hrir_tune_sigma
+ *   For each row, the window bandwidth in grid[0..n_grid) (each > 0, +inf
+ *   allowed) whose HRIR_D_WINDOW solution at the given lambda and threshold
+ *   minimises the spectral distortion of f * g against x (Eq. (17) over the
+ *   m bins of a length-m DFT, magnitudes floored at 1e-12 of their maximum);
+ *   ties keep the earlier grid entry (Sec. IV-E).  sigma_out host f64[n],
+ *   sd_out host f64[n] or null.
+ * Errors: EINVAL (sizes, null pointers, non-finite inputs, bad sigma or
+ * lambda), ENOTPD (a support whose columns are dependent).
+ * ---------------------------------------------------------------------- */
+#define HRIR_D_IDENTITY 0
+#define HRIR_D_CONV 1
+#define HRIR_D_WINDOW 2
+
+int hrir_sparsify(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
+                  const double* sigma, const double* lambda, int32_t target_nnze, double threshold, int32_t k,
+                  int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out, double* err_db_out);
+int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, const double* grid,
+                    int32_t n_grid, double lambda, double threshold, double* sigma_out, double* sd_out);
+
+/* ------------------------------------------------------------------------
  * Render plan: the resonance filter and the sparse tap table on the device.
  * (Eq. (2) rendered as (s * f) * g; Sec. IV-F: cost proportional to the
  * number of kept taps.)

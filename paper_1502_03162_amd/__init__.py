@@ -135,6 +135,9 @@ def _load() -> ctypes.CDLL:
         "stream_info": (c_int, [c_void_p, P_i64]),
         "stream_close": (None, [c_void_p]),
         "stream_loadgen": (c_int, [c_void_p, POINTER(StreamLoad), POINTER(StreamLoadStats)]),
+        "hrir_sparsify": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, c_int32, P_d, P_d, c_int32, c_double, c_int32,
+                                  P_i32, P_f, P_i32, P_d, P_d]),
+        "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_double, P_d, P_d]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -150,7 +153,7 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_des
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
             "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
-            "stream_close", "stream_loadgen")
+            "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma")
 
 
 def lib() -> ctypes.CDLL:
@@ -213,6 +216,47 @@ def factorize(X, lf: int, iters: int, k: int, seed: int = 0, g0=None, lambda0: f
                                _ptr(p, c_int32), _ptr(g, c_float), _ptr(nnz, c_int32), _ptr(err, c_double),
                                None if cost is None else _ptr(cost, c_double)))
     return {"f": f, "G": G, "p": p, "g": g, "nnz": nnz, "err_db": err, "cost": cost}
+
+
+HRIR_D_IDENTITY, HRIR_D_CONV, HRIR_D_WINDOW = 0, 1, 2
+_TRANSFORMS = {"I": HRIR_D_IDENTITY, "C": HRIR_D_CONV, "W": HRIR_D_WINDOW}
+
+
+def sparsify(X, f, k: int, transform: str = "I", sigma=None, lam=None, target_nnze: int = 0,
+             threshold: float = 1e-4) -> dict:
+    """The paper's sparsifier (hrir_sparsify): per-row L1-NNLS with the
+    resonance filter f fixed, transform 'I', 'C' or 'W' (sigma per row or a
+    scalar), lam per row / scalar, or None to search lambda for target_nnze.
+    Returns p, g (k-slot tap table), nnze, lambda, err_db."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    n, m = X.shape
+    sig = None if sigma is None else np.ascontiguousarray(np.broadcast_to(sigma, (n,)), dtype=np.float64)
+    la = None if lam is None else np.ascontiguousarray(np.broadcast_to(lam, (n,)), dtype=np.float64)
+    p = np.empty((n, max(k, 1)), dtype=np.int32)
+    g = np.empty((n, max(k, 1)), dtype=np.float32)
+    nnze = np.empty(n, dtype=np.int32)
+    lam_out = np.empty(n)
+    err = np.empty(n)
+    _check(_lib.hrir_sparsify(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _TRANSFORMS[transform],
+                              None if sig is None else _ptr(sig, c_double), None if la is None else _ptr(la, c_double),
+                              int(target_nnze), float(threshold), int(k), _ptr(p, c_int32), _ptr(g, c_float),
+                              _ptr(nnze, c_int32), _ptr(lam_out, c_double), _ptr(err, c_double)))
+    return {"p": p, "g": g, "nnze": nnze, "lambda": lam_out, "err_db": err}
+
+
+def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4):
+    """Per-row window bandwidth from grid minimising spectral distortion
+    (hrir_tune_sigma).  Returns (sigma, sd)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    gr = np.ascontiguousarray(grid, dtype=np.float64)
+    n, m = X.shape
+    sig = np.empty(n)
+    sd = np.empty(n)
+    _check(_lib.hrir_tune_sigma(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _ptr(gr, c_double), gr.size,
+                                float(lam), float(threshold), _ptr(sig, c_double), _ptr(sd, c_double)))
+    return sig, sd
 
 
 # ---------------------------------------------------------------------------

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
 SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "block.hip",
-           "autotune.cpp", "server.cpp", "loadgen.cpp", "factorize.cpp", "errors.cpp"]
+           "autotune.cpp", "server.cpp", "loadgen.cpp", "factorize.cpp", "sparsify.cpp", "errors.cpp"]
 
 # Per-file extra flags.  The register-window kernel dispatches taps through a
 # tree of wave-uniform scalar branches; the structurizer must leave such

@@ -38,6 +38,8 @@ double l1_weight(double lambda0, int t, int T) {
     return 0.0;
 }
 
+}  // namespace
+
 // In-place Cholesky factorisation of an s x s SPD matrix (lower triangle)
 // followed by the two triangular solves for rhs.  Returns false if not PD.
 bool spd_solve(std::vector<double>& H, int s, double* rhs) {
@@ -65,6 +67,8 @@ bool spd_solve(std::vector<double>& H, int s, double* rhs) {
     }
     return true;
 }
+
+namespace {
 
 struct Problem {
     const double* X;
@@ -159,6 +163,9 @@ double residual_energy_row(const double* x, int m, const double* f, int lf, cons
     return e;
 }
 
+
+}  // namespace
+
 // Lawson-Hanson active set on the normal equations: min 1/2 y^T H y - c^T y,
 // y >= 0, with H = A^T A (s x s) and c = A^T x.
 int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y) {
@@ -218,8 +225,6 @@ int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int 
     }
     return HRIR_OK;
 }
-
-}  // namespace
 
 }  // namespace hrir
 

@@ -18,6 +18,14 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 const char* last_error();
 
+// In-place Cholesky solve of the s x s SPD system H y = rhs (rhs overwritten
+// with y).  Returns false if H is not positive definite.
+bool spd_solve(std::vector<double>& H, int s, double* rhs);
+
+// Lawson-Hanson active-set solution of min 1/2 y^T H y - c^T y over y >= 0,
+// H the s x s normal matrix.  Status code as in hrir.h.
+int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y);
+
 // Runs body(i) for i in [0, n) on up to hardware_concurrency threads with
 // static contiguous chunks.  Results must not depend on the thread count:
 // callers write disjoint outputs and reduce sequentially afterwards.

@@ -1,0 +1,351 @@
+// The paper's own sparsifier (Sec. III-D): with the resonance filter f
+// fixed, each reflection filter solves the penalised L1-NNLS problem of
+// Eq. (14),
+//     min_g ||D (T(f) g - x)||^2 + lambda sum(g),  g >= 0,
+// for a residual transform D (identity, the Gaussian convolution of Eq. (15)
+// or the Gaussian time window of Eq. (16)); entries at or below a threshold
+// (1e-4 in the paper) are then discarded.  lambda may be given per filter or
+// searched for a target NNZE; the window bandwidth may be tuned per HRIR over
+// a grid by spectral distortion (Sec. IV-E).  Host, FP64.
+//
+// With A = D T(f) and b = D x the problem is min 1/2 g^T H g - c^T g over
+// g >= 0 with H = A^T A and c = A^T b - lambda / 2, solved by the same
+// active-set NNLS as the top-K refit.  H depends only on (transform, sigma),
+// so it is formed once per bandwidth and shared by every filter.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hrir_internal.h"
+
+namespace hrir {
+namespace {
+
+struct Design {
+    int m = 0, lg = 0;
+    std::vector<double> A;     // m x lg, row-major: A = D T(f)
+    std::vector<double> D;     // m x m (dense), or empty for a diagonal / identity
+    std::vector<double> dg;    // diagonal of D (window), empty otherwise
+    std::vector<double> H;     // lg x lg: A^T A
+};
+
+double gauss_conv(double k, double sigma) {
+    return std::exp(-(k * k) / (2.0 * sigma * sigma)) / (sigma * std::sqrt(2.0 * M_PI));
+}
+
+// A = D T(f), with T(f)[i][j] = f[i - j] (m = lf + lg - 1 rows).
+void build_design(Design& d, const double* f, int lf, int lg, int transform, double sigma) {
+    const int m = lf + lg - 1;
+    d.m = m;
+    d.lg = lg;
+    d.D.clear();
+    d.dg.clear();
+    if (transform == HRIR_D_WINDOW && std::isfinite(sigma)) {
+        d.dg.resize(m);
+        for (int i = 0; i < m; ++i) d.dg[i] = std::exp(-((double)i * i) / (sigma * sigma));
+    } else if (transform == HRIR_D_CONV) {
+        d.D.resize((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) d.D[(size_t)i * m + j] = gauss_conv((double)(i - j), sigma);
+    }
+    d.A.assign((size_t)m * lg, 0.0);
+    for (int j = 0; j < lg; ++j)
+        for (int q = 0; q < lf; ++q) d.A[(size_t)(j + q) * lg + j] = f[q];
+    if (!d.dg.empty()) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < lg; ++j) d.A[(size_t)i * lg + j] *= d.dg[i];
+    } else if (!d.D.empty()) {
+        std::vector<double> T = d.A;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < lg; ++j) {
+                double v = 0.0;
+                for (int q = j; q < std::min(m, j + lf); ++q) v += d.D[(size_t)i * m + q] * T[(size_t)q * lg + j];
+                d.A[(size_t)i * lg + j] = v;
+            }
+    }
+    d.H.assign((size_t)lg * lg, 0.0);
+    for (int a = 0; a < lg; ++a)
+        for (int b = a; b < lg; ++b) {
+            double v = 0.0;
+            for (int i = 0; i < m; ++i) v += d.A[(size_t)i * lg + a] * d.A[(size_t)i * lg + b];
+            d.H[(size_t)a * lg + b] = v;
+            d.H[(size_t)b * lg + a] = v;
+        }
+}
+
+// c0 = A^T (D x): the lambda-free part of the linear term.
+void design_rhs(const Design& d, const double* x, std::vector<double>& c0) {
+    std::vector<double> b(d.m);
+    for (int i = 0; i < d.m; ++i) {
+        if (!d.dg.empty()) {
+            b[i] = d.dg[i] * x[i];
+        } else if (!d.D.empty()) {
+            double v = 0.0;
+            for (int q = 0; q < d.m; ++q) v += d.D[(size_t)i * d.m + q] * x[q];
+            b[i] = v;
+        } else {
+            b[i] = x[i];
+        }
+    }
+    c0.assign(d.lg, 0.0);
+    for (int i = 0; i < d.m; ++i)
+        for (int j = 0; j < d.lg; ++j) c0[j] += d.A[(size_t)i * d.lg + j] * b[i];
+}
+
+// One L1-NNLS solve and the discard; returns the status and the NNZE.
+int solve_one(const Design& d, const std::vector<double>& c0, double lambda, double thresh, std::vector<double>& c,
+              double* g, int* nnze) {
+    c.resize(d.lg);
+    for (int j = 0; j < d.lg; ++j) c[j] = c0[j] - 0.5 * lambda;
+    const int rc = nnls_normal(d.H, c, d.lg, g);
+    if (rc) return rc;
+    int nz = 0;
+    for (int j = 0; j < d.lg; ++j) {
+        if (std::fabs(g[j]) <= thresh) g[j] = 0.0;
+        nz += g[j] != 0.0;
+    }
+    *nnze = nz;
+    return HRIR_OK;
+}
+
+// Geometric bisection on [1e-12, 1] * lambda_max for the smallest lambda whose
+// solution keeps at most `target` entries (lambda = 0 if it already does).
+int search_lambda(const Design& d, const std::vector<double>& c0, int target, double thresh, double* g,
+                  double* lambda_out, int* nnze_out) {
+    std::vector<double> c, gt(d.lg);
+    int nz = 0;
+    int rc = solve_one(d, c0, 0.0, thresh, c, g, &nz);
+    if (rc) return rc;
+    if (nz <= target) {
+        *lambda_out = 0.0;
+        *nnze_out = nz;
+        return HRIR_OK;
+    }
+    double cmax = 0.0;
+    for (double v : c0) cmax = std::max(cmax, v);
+    double hi = 2.0 * cmax, lo = hi * 1e-12;
+    std::fill(g, g + d.lg, 0.0);
+    int nz_hi = 0;
+    for (int it = 0; it < 50; ++it) {
+        const double mid = std::sqrt(lo * hi);
+        rc = solve_one(d, c0, mid, thresh, c, gt.data(), &nz);
+        if (rc) return rc;
+        if (nz <= target) {
+            hi = mid;
+            nz_hi = nz;
+            std::memcpy(g, gt.data(), sizeof(double) * d.lg);
+        } else {
+            lo = mid;
+        }
+    }
+    *lambda_out = hi;
+    *nnze_out = nz_hi;
+    return HRIR_OK;
+}
+
+// Magnitudes of the length-m DFT through a cosine / sine table built once.
+struct Dft {
+    int m = 0;
+    std::vector<double> cs, sn;    // m x m
+    explicit Dft(int m_) : m(m_), cs((size_t)m_ * m_), sn((size_t)m_ * m_) {
+        for (int k = 0; k < m; ++k)
+            for (int t = 0; t < m; ++t) {
+                const double ang = -2.0 * M_PI * (double)(((int64_t)k * t) % m) / (double)m;
+                cs[(size_t)k * m + t] = std::cos(ang);
+                sn[(size_t)k * m + t] = std::sin(ang);
+            }
+    }
+    // |DFT(h)| floored at 1e-12 of its maximum
+    void floored_magnitude(const double* h, double* mag) const {
+        double mx = 0.0;
+        for (int k = 0; k < m; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int t = 0; t < m; ++t) {
+                re += h[t] * cs[(size_t)k * m + t];
+                im += h[t] * sn[(size_t)k * m + t];
+            }
+            mag[k] = std::hypot(re, im);
+            mx = std::max(mx, mag[k]);
+        }
+        const double fl = 1e-12 * std::max(mx, 1e-300);
+        for (int k = 0; k < m; ++k) mag[k] = std::max(mag[k], fl);
+    }
+};
+
+// Spectral distortion (Eq. (17)) between two floored magnitude spectra.
+double spectral_distortion(const double* a, const double* b, int m) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double v = 20.0 * std::log10(a[k] / b[k]);
+        acc += v * v;
+    }
+    return std::sqrt(acc / m);
+}
+
+void convolve(const double* f, int lf, const double* g, int lg, double* y) {
+    const int m = lf + lg - 1;
+    for (int t = 0; t < m; ++t) y[t] = 0.0;
+    for (int j = 0; j < lg; ++j)
+        if (g[j] != 0.0)
+            for (int q = 0; q < lf; ++q) y[j + q] += f[q] * g[j];
+}
+
+int check_common(const double* X, int n, int m, const double* f, int lf, const char* fn) {
+    if (!X || !f) return fail(HRIR_EINVAL, "%s: null pointer", fn);
+    if (n < 1 || lf < 1 || m < lf) return fail(HRIR_EINVAL, "%s: need n >= 1 and 1 <= lf <= m", fn);
+    if ((int64_t)m * m > (int64_t)1 << 26) return fail(HRIR_EINVAL, "%s: m=%d too large", fn, m);
+    for (int64_t i = 0; i < (int64_t)n * m; ++i)
+        if (!std::isfinite(X[i])) return fail(HRIR_EINVAL, "%s: X has a non-finite entry", fn);
+    for (int q = 0; q < lf; ++q)
+        if (!std::isfinite(f[q])) return fail(HRIR_EINVAL, "%s: f has a non-finite entry", fn);
+    return HRIR_OK;
+}
+
+}  // namespace
+}  // namespace hrir
+
+using hrir::fail;
+
+extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
+                             const double* sigma, const double* lambda, int32_t target_nnze, double threshold,
+                             int32_t k, int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out,
+                             double* err_db_out) {
+    hrir::clear_error();
+    int rc = hrir::check_common(X, n, m, f, lf, "hrir_sparsify");
+    if (rc) return rc;
+    if (!p_out || !g_out) return fail(HRIR_EINVAL, "hrir_sparsify: null output pointer");
+    if (transform != HRIR_D_IDENTITY && transform != HRIR_D_CONV && transform != HRIR_D_WINDOW)
+        return fail(HRIR_EINVAL, "hrir_sparsify: unknown transform %d", transform);
+    if (transform != HRIR_D_IDENTITY) {
+        if (!sigma) return fail(HRIR_EINVAL, "hrir_sparsify: transform %d needs sigma", transform);
+        for (int i = 0; i < n; ++i)
+            if (!(sigma[i] > 0.0) || (transform == HRIR_D_CONV && !std::isfinite(sigma[i])))
+                return fail(HRIR_EINVAL, "hrir_sparsify: sigma[%d]=%g invalid", i, sigma[i]);
+    }
+    if (lambda) {
+        for (int i = 0; i < n; ++i)
+            if (!(lambda[i] >= 0.0) || !std::isfinite(lambda[i]))
+                return fail(HRIR_EINVAL, "hrir_sparsify: lambda[%d]=%g invalid", i, lambda[i]);
+    } else if (target_nnze < 0) {
+        return fail(HRIR_EINVAL, "hrir_sparsify: target_nnze=%d < 0", target_nnze);
+    }
+    if (!(threshold >= 0.0)) return fail(HRIR_EINVAL, "hrir_sparsify: threshold < 0");
+    if (k < 1) return fail(HRIR_EINVAL, "hrir_sparsify: k=%d < 1", k);
+    const int lg = m - lf + 1;
+
+    // one design per distinct bandwidth, in order of first use
+    std::vector<double> keys;
+    std::vector<int> which(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const double s = transform == HRIR_D_IDENTITY ? INFINITY : sigma[i];
+        int w = -1;
+        for (size_t u = 0; u < keys.size(); ++u)
+            if (keys[u] == s || (std::isinf(keys[u]) && std::isinf(s))) w = (int)u;
+        if (w < 0) {
+            w = (int)keys.size();
+            keys.push_back(s);
+        }
+        which[i] = w;
+    }
+    std::vector<hrir::Design> designs(keys.size());
+    hrir::parallel_for((int64_t)keys.size(), [&](int64_t u) {
+        hrir::build_design(designs[u], f, lf, lg, transform, keys[u]);
+    });
+
+    std::vector<int> status(n, 0);
+    hrir::parallel_for(n, [&](int64_t i) {
+        const hrir::Design& d = designs[which[i]];
+        std::vector<double> c0, c, g(lg);
+        hrir::design_rhs(d, X + (size_t)i * m, c0);
+        double lam = 0.0;
+        int nz = 0;
+        int st;
+        if (lambda) {
+            lam = lambda[i];
+            st = hrir::solve_one(d, c0, lam, threshold, c, g.data(), &nz);
+        } else {
+            st = hrir::search_lambda(d, c0, target_nnze, threshold, g.data(), &lam, &nz);
+        }
+        status[i] = st;
+        if (st) return;
+        // the k largest kept entries (ties to the lower position), ascending positions
+        std::vector<int> idx;
+        for (int j = 0; j < lg; ++j)
+            if (g[j] != 0.0) idx.push_back(j);
+        if ((int)idx.size() > k) {
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return g[a] > g[b]; });
+            idx.resize(k);
+            std::sort(idx.begin(), idx.end());
+        }
+        std::vector<double> gk(lg, 0.0);
+        for (int a = 0; a < k; ++a) {
+            const bool real = a < (int)idx.size();
+            p_out[(size_t)i * k + a] = real ? idx[a] : 0;
+            g_out[(size_t)i * k + a] = real ? (float)g[idx[a]] : 0.0f;
+            if (real) gk[idx[a]] = g[idx[a]];
+        }
+        if (nnze_out) nnze_out[i] = nz;
+        if (lambda_out) lambda_out[i] = lam;
+        if (err_db_out) {
+            const double* x = X + (size_t)i * m;
+            std::vector<double> y(m);
+            hrir::convolve(f, lf, gk.data(), lg, y.data());
+            double e = 0.0, ex = 0.0;
+            for (int t = 0; t < m; ++t) {
+                e += (x[t] - y[t]) * (x[t] - y[t]);
+                ex += x[t] * x[t];
+            }
+            err_db_out[i] = (ex > 0.0 && e > 0.0) ? 10.0 * std::log10(e / ex) : (e > 0.0 ? INFINITY : -INFINITY);
+        }
+    });
+    for (int i = 0; i < n; ++i)
+        if (status[i]) return fail(status[i], "hrir_sparsify: NNLS failed on row %d", i);
+    return HRIR_OK;
+}
+
+extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
+                               const double* grid, int32_t n_grid, double lambda, double threshold,
+                               double* sigma_out, double* sd_out) {
+    hrir::clear_error();
+    int rc = hrir::check_common(X, n, m, f, lf, "hrir_tune_sigma");
+    if (rc) return rc;
+    if (!grid || n_grid < 1 || !sigma_out) return fail(HRIR_EINVAL, "hrir_tune_sigma: empty grid or null output");
+    for (int u = 0; u < n_grid; ++u)
+        if (!(grid[u] > 0.0)) return fail(HRIR_EINVAL, "hrir_tune_sigma: grid[%d]=%g must be > 0", u, grid[u]);
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(HRIR_EINVAL, "hrir_tune_sigma: lambda invalid");
+    if (!(threshold >= 0.0)) return fail(HRIR_EINVAL, "hrir_tune_sigma: threshold < 0");
+    const int lg = m - lf + 1;
+    std::vector<hrir::Design> designs(n_grid);
+    hrir::parallel_for(n_grid, [&](int64_t u) {
+        hrir::build_design(designs[u], f, lf, lg, HRIR_D_WINDOW, grid[u]);
+    });
+    const hrir::Dft dft(m);
+    std::vector<int> status(n, 0);
+    hrir::parallel_for(n, [&](int64_t i) {
+        const double* x = X + (size_t)i * m;
+        std::vector<double> c0, c, g(lg), y(m), mx(m), my(m);
+        dft.floored_magnitude(x, mx.data());
+        double best = INFINITY, best_s = grid[0];
+        for (int u = 0; u < n_grid; ++u) {
+            hrir::design_rhs(designs[u], x, c0);
+            int nz = 0;
+            const int st = hrir::solve_one(designs[u], c0, lambda, threshold, c, g.data(), &nz);
+            if (st) {
+                status[i] = st;
+                return;
+            }
+            hrir::convolve(f, lf, g.data(), lg, y.data());
+            dft.floored_magnitude(y.data(), my.data());
+            const double sd = hrir::spectral_distortion(mx.data(), my.data(), m);
+            if (sd < best) {
+                best = sd;
+                best_s = grid[u];
+            }
+        }
+        sigma_out[i] = best_s;
+        if (sd_out) sd_out[i] = best;
+    });
+    for (int i = 0; i < n; ++i)
+        if (status[i]) return fail(status[i], "hrir_tune_sigma: NNLS failed on row %d", i);
+    return HRIR_OK;
+}
