@@ -57,23 +57,45 @@ def measured_traffic(name: str):
     return d.get("bytes_per_launch")
 
 
-def time_launches(fn, steps: int, warmup: int):
+def time_launches(fn, steps: int, warmup: int, per_launch=None):
     """Run fn() warmup times, then time `steps` calls with HIP events on the
-    current stream (the stream the kernels are launched on)."""
+    current stream (the stream the kernels are launched on).  Returns the
+    mean ms per call over the bracket and the wall time; if per_launch is a
+    list, it receives each call's own event-pair duration."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_launch is not None else None
     t0 = time.perf_counter()
     e0.record(st)
-    for _ in range(steps):
+    for i in range(steps):
+        if marks:
+            marks[i].record(st)
         fn()
+    if marks:
+        marks[steps].record(st)
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if marks:
+        per_launch.extend(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
     return e0.elapsed_time(e1) / steps, wall
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(r, srcs, p, g, lg, jobs, n_src_sample: int, chunk: int = 4):
@@ -97,6 +119,7 @@ def cpu_baseline(r, srcs, p, g, lg, jobs, n_src_sample: int, chunk: int = 4):
         n_rows += len(sel)
         del rows
     return {"value": n_out / dt, "unit": "output samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{n_src_sample} of the 64 sources with all their {n_rows} (direction, ear) rows "
                       f"({n_out} outputs), FP64 oracle in chunks of {chunk} sources, {dt:.1f} s"}
 
@@ -264,7 +287,9 @@ def main():
                     help="fused render kernel (quad: default)")
     ap.add_argument("--cpu-sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="dense,fft", help="comparison legs to time: dense, fft (comma list, or none)")
+    ap.add_argument("--legs", default="dense,fft,unfused",
+                    help="comparison legs to time: dense, fft, unfused (comma list, or none)")
+    ap.add_argument("--k-sweep", default="8,32", help="other K values to factorize and time (comma list, or empty)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
@@ -315,7 +340,8 @@ def main():
     log(f"render ({info['kernel']}): {len(jobs)} rows, {n_out} outputs, tiles {info['tiles']} of {info['tile']}, "
         f"grid {info['grid']}")
 
-    ms, wall = time_launches(lambda: batch.render(src, out), args.steps, args.warmup)
+    per = []
+    ms, wall = time_launches(lambda: batch.render(src, out), args.steps, args.warmup, per)
     value = n_out / (ms * 1e-3)
     alg_bytes = 4.0 * n_out + 4.0 * n_src * ns       # each output written once, each source read once
     achieved = alg_bytes / (ms * 1e-3) / 1e9
@@ -347,6 +373,34 @@ def main():
         legs["fft_ola"] = {"ms_per_step": by[best], "value": n_out / (by[best] * 1e-3), "best_nfft": int(best),
                            "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
 
+    if "unfused" in want:
+        ub = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], flags=H.SPCONV_UNFUSED)
+        ums, _ = time_launches(lambda: ub.render(src, out), args.leg_steps, 1)
+        legs["unfused"] = {"ms_per_step": ums, "value": n_out / (ums * 1e-3), "kernel": "k_resonance + k_gather",
+                           "speedup_fused": ums / ms,
+                           "note": "z = r * s written to HBM, then a gather kernel reads it back"}
+        log(f"unfused (z through HBM): {ums:.3f} ms/step, fused speedup {ums / ms:.2f}x")
+        ub.close()
+        torch.cuda.empty_cache()
+
+    k_sweep = {}
+    for kk in [int(x) for x in args.k_sweep.split(",") if x]:
+        t1 = time.perf_counter()
+        fk = H.factorize(hs.h, lf, args.fact_iters, kk, seed=7, lambda0=0.2, want_cost=False)
+        ek = fk["err_db"]
+        ek_agg = float(10 * np.log10(np.sum(10 ** (ek / 10) * np.sum(hs.h ** 2, axis=1)) / np.sum(hs.h ** 2)))
+        pk = H.Plan(fk["f"].astype(np.float32), fk["p"], fk["g"], lg)
+        bk = H.Batch(pk, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], tile=args.tile, group=args.group)
+        kms, _ = time_launches(lambda: bk.render(src, out), args.steps, args.warmup)
+        kach = alg_bytes / (kms * 1e-3) / 1e9
+        k_sweep[str(kk)] = {"ms_per_step": kms, "value": n_out / (kms * 1e-3), "achieved_GBps": kach,
+                            "frac": kach / HBM_PEAK_GBS, "E_dB_aggregate": ek_agg, "E_dB_worst_filter": float(ek.max()),
+                            "flop_per_output": 2 * kk + 2 * lf / (2 * dps)}
+        log(f"K={kk}: {kms:.3f} ms/step, {n_out / (kms * 1e-3):.4g} samples/s, {kach:.0f} GB/s, E_dB {ek_agg:.2f} "
+            f"(factorized in {time.perf_counter() - t1:.1f} s)")
+        bk.close()
+        pk.close()
+
     if args.copy_calib:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         c = torch.empty_like(a)
@@ -368,6 +422,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_median": float(np.median(per)),
+        "ms_min": float(np.min(per)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -386,6 +442,7 @@ def main():
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters},
         "legs": legs,
+        "k_sweep": k_sweep,
         "uneven": uneven,
         "block_latency": latency,
         "serving": serving,
