@@ -273,6 +273,58 @@ def bench_serving(H, fac, r, lg, args):
             "load_definition": "offered block rate / measured saturation rate of the loop"}
 
 
+def spectral_distortion_rows(X, Y) -> np.ndarray:
+    """Per-row SD of Y against X over the M bins of a length-M DFT (|.|
+    floored at 1e-12 of each row's maximum)."""
+    A = np.abs(np.fft.fft(X, axis=1))
+    B = np.abs(np.fft.fft(Y, axis=1))
+    A = np.maximum(A, 1e-12 * A.max(axis=1, keepdims=True))
+    B = np.maximum(B, 1e-12 * B.max(axis=1, keepdims=True))
+    return np.sqrt(np.mean((20 * np.log10(A / B)) ** 2, axis=1))
+
+
+def bench_sparsifier(H, hs, fac, lf, lg, k):
+    """Quality of the paper's own sparsifier (L1-NNLS, Eq. (14), with the
+    trained f fixed; lambda searched per filter for at most k taps) against
+    top-k with NNLS refit, on the full 1,250-direction set."""
+    X = hs.h
+    f = fac["f"]
+
+    def scores(p, g):
+        G = np.zeros((X.shape[0], lg))
+        for i in range(X.shape[0]):
+            np.add.at(G[i], p[i], g[i].astype(np.float64))
+        Y = np.stack([np.convolve(f, G[i]) for i in range(X.shape[0])])
+        e = float(10 * np.log10(np.sum((X - Y) ** 2) / np.sum(X ** 2)))
+        return e, float(np.mean(spectral_distortion_rows(X, Y))), float(np.mean(np.count_nonzero(G, axis=1)))
+
+    res = {}
+    e, sd, nz = scores(fac["p"], fac["g"])
+    res["topk_refit"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz}
+    t = time.perf_counter()
+    r = H.sparsify(X, f, k, "I", target_nnze=k)
+    e, sd, nz = scores(r["p"], r["g"])
+    res["l1_nnls_identity"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz, "host_s": time.perf_counter() - t}
+    t = time.perf_counter()
+    grid = [15.0 + 2.0 * i for i in range(25)] + [100.0, 160.0, 250.0, float("inf")]
+    sig, sd_tuned = H.tune_sigma(X, f, grid)
+    _, sd_id = H.tune_sigma(X, f, [float("inf")])
+    # the paper's table: SD at lambda = 0, identity against per-HRIR tuned sigma
+    res["sigma_table_lambda0"] = {"identity_SD_dB_mean": float(np.mean(sd_id)),
+                                  "tuned_SD_dB_mean": float(np.mean(sd_tuned)),
+                                  "relative_drop": float(1 - np.mean(sd_tuned) / np.mean(sd_id))}
+    log(f"sigma tuning at lambda = 0: SD {np.mean(sd_id):.3f} -> {np.mean(sd_tuned):.3f} dB")
+    r = H.sparsify(X, f, k, "W", sigma=sig, target_nnze=k)
+    e, sd, nz = scores(r["p"], r["g"])
+    res["l1_nnls_window_tuned_sigma"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz,
+                                         "sigma_median": float(np.median(sig)), "host_s": time.perf_counter() - t}
+    for name, v in res.items():
+        if "E_dB" not in v:
+            continue
+        log(f"sparsifier {name}: E_dB {v['E_dB']:.2f}, SD {v['SD_dB_mean']:.3f} dB, NNZE {v['nnze_mean']:.2f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +348,7 @@ def main():
     ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds per streaming-loop load level (0: skip)")
+    ap.add_argument("--no-sparsifier", action="store_true", help="skip the L1-NNLS sparsifier quality section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run 3 device copies of 1 GiB (read 1 GiB + write 1 GiB each) to calibrate counters")
     args = ap.parse_args()
@@ -413,6 +466,7 @@ def main():
     uneven = None if args.no_uneven else bench_uneven(H, torch, dev, fac, r, lf, lg, args)
     latency = bench_latency(H, torch, dev, fac, r, lg, args) if args.latency_ticks > 0 else None
     serving = bench_serving(H, fac, r, lg, args) if args.serve_seconds > 0 else None
+    sparsifier = None if args.no_sparsifier else bench_sparsifier(H, hs, fac, lf, lg, args.k)
 
     res = {
         "metric": METRIC,
@@ -440,7 +494,7 @@ def main():
                      "kernel": {"quad": "k_render_quad<32,16>", "register_window": "k_render_rw<32>",
                                 "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
-                    "fact_iters": args.fact_iters},
+                    "fact_iters": args.fact_iters, "sparsifiers": sparsifier},
         "legs": legs,
         "k_sweep": k_sweep,
         "uneven": uneven,

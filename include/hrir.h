@@ -421,6 +421,50 @@ int stream_info(const hrir_server* server, int64_t* info8);
 void stream_close(hrir_server* server);
 
 /* ------------------------------------------------------------------------
+ * Direction-conditioned surrogate: a ReLU MLP that predicts a direction's
+ * reflection filters (the sparse non-negative factor of Eq. (1)) from
+ * (sin az, cos az, sin el, cos el), trained on factorizations of the
+ * measured directions (Alg. 1) so that directions between them get filters
+ * too.  Layer l maps sizes[l] -> sizes[l + 1] with ReLU (the output layer
+ * too, so taps are non-negative).  FP32 master weights; activations are
+ * stored as bfloat16 between layers (inputs included, round to nearest
+ * even); products accumulate in FP32 on MFMA; loss = mean squared error
+ * over all outputs; Adam (beta 0.9 / 0.999, eps 1e-8) with bias correction.
+ *
+ * mlp_create      sizes[0..n_layers], each 1..4096; max_batch rows per pass
+ *                 (1..2^20).  Parameters start at zero: set them first.
+ * mlp_num_params  total parameter count (-1 for a null handle).
+ * mlp_set_params  host f32 flat parameters: W0 (sizes[0] x sizes[1],
+ *                 row-major), b0, W1, b1, ...; resets Adam's moments and
+ *                 step.  Synchronous.
+ * mlp_get_params  the same layout back to host memory.  Synchronous.
+ * mlp_forward     d_x device f32 [n][sizes[0]] -> d_y device f32
+ *                 [n][sizes[n_layers]], any n >= 0 (chunks of max_batch).
+ * mlp_grads       one forward + backward pass on n <= max_batch rows with
+ *                 targets d_t device f32 [n][out], no update; gradients to
+ *                 host f32 (parameter layout) and the loss, if non-null.
+ * mlp_train       `steps` full-batch Adam steps on (d_x, d_t); the step is a
+ *                 HIP graph captured on the first call for these buffers,
+ *                 batch and learning rate, then replayed.  loss (host, may be
+ *                 null) receives the loss of the last step's forward pass
+ *                 (the call then waits for the GPU).
+ * Device buffers belong to the caller and must stay valid until the stream
+ * reaches the work.  Errors: EINVAL, ENOMEM, EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct hrir_mlp hrir_mlp;
+
+int mlp_create(const int32_t* sizes, int32_t n_layers, int32_t max_batch, hrir_mlp** out);
+int64_t mlp_num_params(const hrir_mlp* mlp);
+int mlp_set_params(hrir_mlp* mlp, const float* params, int64_t n);
+int mlp_get_params(const hrir_mlp* mlp, float* params, int64_t n);
+int mlp_forward(hrir_mlp* mlp, const float* d_x, int32_t n, float* d_y, void* stream);
+int mlp_grads(hrir_mlp* mlp, const float* d_x, const float* d_t, int32_t n, float* grads, double* loss,
+              void* stream);
+int mlp_train(hrir_mlp* mlp, const float* d_x, const float* d_t, int32_t n, int32_t steps, float lr, double* loss,
+              void* stream);
+void mlp_destroy(hrir_mlp* mlp);
+
+/* ------------------------------------------------------------------------
  * Load generator for the streaming loop (a client of the stream_* calls
  * above, for measurement).  Open loop: block arrivals form a Poisson process
  * of rate_hz blocks/s over all streams for duration_s seconds; each arrival

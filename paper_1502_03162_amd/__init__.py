@@ -138,6 +138,14 @@ def _load() -> ctypes.CDLL:
         "hrir_sparsify": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, c_int32, P_d, P_d, c_int32, c_double, c_int32,
                                   P_i32, P_f, P_i32, P_d, P_d]),
         "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_double, P_d, P_d]),
+        "mlp_create": (c_int, [P_i32, c_int32, c_int32, POINTER(c_void_p)]),
+        "mlp_num_params": (c_int64, [c_void_p]),
+        "mlp_set_params": (c_int, [c_void_p, P_f, c_int64]),
+        "mlp_get_params": (c_int, [c_void_p, P_f, c_int64]),
+        "mlp_forward": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+        "mlp_grads": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, P_f, P_d, c_void_p]),
+        "mlp_train": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_float, P_d, c_void_p]),
+        "mlp_destroy": (None, [c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -153,7 +161,9 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_des
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
             "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
-            "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma")
+            "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma",
+            "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
+            "mlp_train", "mlp_destroy")
 
 
 def lib() -> ctypes.CDLL:
@@ -613,6 +623,73 @@ class Server:
     def close(self):
         if getattr(self, "_h", None):
             _lib.stream_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
+
+
+class Mlp:
+    """Direction-conditioned surrogate network (mlp_*): ReLU layers with the
+    given sizes; parameters as a list of (W [k_in][k_out], b [k_out])."""
+
+    def __init__(self, sizes, max_batch: int):
+        self.sizes = [int(x) for x in sizes]
+        sz = np.asarray(self.sizes, dtype=np.int32)
+        hd = c_void_p()
+        _check(_lib.mlp_create(_ptr(sz, c_int32), len(self.sizes) - 1, int(max_batch), byref(hd)))
+        self._h = hd
+        self.n_params = int(_lib.mlp_num_params(hd))
+
+    def set_params(self, params):
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                               for W, b in params]).astype(np.float32)
+        _check(_lib.mlp_set_params(self._h, _ptr(flat, c_float), flat.size))
+
+    def _unflatten(self, flat):
+        out, o = [], 0
+        for k_in, k_out in zip(self.sizes[:-1], self.sizes[1:]):
+            W = flat[o:o + k_in * k_out].reshape(k_in, k_out)
+            o += k_in * k_out
+            b = flat[o:o + k_out]
+            o += k_out
+            out.append((W, b))
+        return out
+
+    def get_params(self):
+        flat = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib.mlp_get_params(self._h, _ptr(flat, c_float), flat.size))
+        return self._unflatten(flat)
+
+    def forward(self, x, y, stream=None):
+        """x: device tensor [n][sizes[0]], y: device tensor [n][sizes[-1]] (float32)."""
+        xp, _ = _f32(x)
+        yp, _ = _f32(y)
+        _check(_lib.mlp_forward(self._h, xp, int(x.shape[0]), yp, c_void_p(_stream_handle(stream))))
+
+    def grads(self, x, t, stream=None):
+        flat = np.empty(self.n_params, dtype=np.float32)
+        loss = c_double()
+        xp, _ = _f32(x)
+        tp, _ = _f32(t)
+        _check(_lib.mlp_grads(self._h, xp, tp, int(x.shape[0]), _ptr(flat, c_float), byref(loss),
+                              c_void_p(_stream_handle(stream))))
+        return loss.value, self._unflatten(flat)
+
+    def train(self, x, t, steps: int, lr: float, stream=None) -> float:
+        loss = c_double()
+        xp, _ = _f32(x)
+        tp, _ = _f32(t)
+        _check(_lib.mlp_train(self._h, xp, tp, int(x.shape[0]), int(steps), float(lr), byref(loss),
+                              c_void_p(_stream_handle(stream))))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

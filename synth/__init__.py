@@ -185,3 +185,16 @@ def random_taps(seed: int, n_filters: int, k: int, lg: int, nnz_min: int | None 
 def g0(seed: int, n: int, lg: int) -> np.ndarray:
     """Initial reflection matrix G0 ~ U(0, 1] (Alg. 1's random start)."""
     return 1.0 - np.random.default_rng(seed).uniform(0.0, 1.0, size=(n, lg))
+
+
+def mlp_params(seed: int, sizes):
+    """Initial surrogate parameters: He-uniform weights
+    U(-sqrt(6 / k_in), +sqrt(6 / k_in)) and zero biases, float64, as a list
+    of (W [k_in][k_out], b [k_out]); the same arrays seed both the library
+    and the oracle."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k_in, k_out in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / k_in)
+        out.append((rng.uniform(-lim, lim, (k_in, k_out)), np.zeros(k_out)))
+    return out

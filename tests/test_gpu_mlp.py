@@ -1,0 +1,147 @@
+"""GPU tests of the surrogate network (mlp_* in include/hrir.h) against the
+FP64 oracle (oracle/mlp.py) on the same float32 parameters and inputs.
+
+Tolerance: both sides round every hidden activation to bfloat16 from their
+own pre-activation (FP32 accumulation on the GPU, FP64 in the oracle).  The
+two pre-activations differ by ~1e-7 relative, so a rounding decision flips
+only for values within that of a bf16 rounding boundary (probability ~1e-7 /
+2^-8 per element) and a flip moves one activation by one bf16 step (2^-8
+relative).  Over the whole output that stays far below 1e-3 relative L2,
+the bound used here; gradients inherit the same perturbation."""
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [4, 256, 256, 256, 256, 400]
+TOL = 1e-3
+
+
+def H():
+    import paper_1502_03162_amd
+    return paper_1502_03162_amd
+
+
+def _f32_params(params):
+    return [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for W, b in params]
+
+
+def _inputs(seed, n):
+    rng = np.random.default_rng(seed)
+    az = rng.uniform(-np.pi, np.pi, n)
+    el = rng.uniform(-np.pi / 4, 1.3 * np.pi, n)
+    return M.features(az, el).astype(np.float32)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_forward_matches_oracle(dev):
+    import torch
+    h = H()
+    params = _f32_params(synth.mlp_params(1, SIZES))
+    X = _inputs(2, 1000)
+    net = h.Mlp(SIZES, max_batch=384)            # several chunks, the last one ragged
+    net.set_params(params)
+    x = torch.from_numpy(X).to(dev)
+    y = torch.full((1000, SIZES[-1]), float("nan"), device=dev)
+    net.forward(x, y)
+    torch.cuda.synchronize()
+    yo, _ = M.forward(params, X.astype(np.float64))
+    yg = y.cpu().numpy()
+    assert np.all(np.isfinite(yg)) and np.all(yg >= 0)
+    assert _rel(yg, yo) <= TOL
+    back = net.get_params()
+    for (W, b), (Wo, bo) in zip(back, params):
+        np.testing.assert_array_equal(W, Wo.astype(np.float32))
+        np.testing.assert_array_equal(b, bo.astype(np.float32))
+    net.close()
+
+
+@pytest.mark.parametrize("sizes", [SIZES, [4, 33, 70, 5], [3, 64, 1]])
+def test_gradients_match_oracle(dev, sizes):
+    import torch
+    h = H()
+    rng = np.random.default_rng(3)
+    params = _f32_params([(W, rng.standard_normal(b.shape) * 0.05) for W, b in synth.mlp_params(4, sizes)])
+    n = 777
+    X = rng.standard_normal((n, sizes[0])).astype(np.float32)
+    T = np.abs(rng.standard_normal((n, sizes[-1]))).astype(np.float32) * 0.3
+    net = h.Mlp(sizes, max_batch=1024)
+    net.set_params(params)
+    loss, grads = net.grads(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev))
+    lo, go = M.loss_and_grads(params, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lo) <= TOL * lo
+    for (gW, gb), (oW, ob) in zip(grads, go):
+        assert _rel(gW, oW) <= TOL
+        assert _rel(gb, ob) <= TOL
+    net.close()
+
+
+def test_one_adam_step_matches_oracle(dev):
+    import torch
+    h = H()
+    params = _f32_params(synth.mlp_params(5, SIZES))
+    X = _inputs(6, 500)
+    T = (np.abs(np.random.default_rng(7).standard_normal((500, SIZES[-1]))) * 0.1).astype(np.float32)
+    net = h.Mlp(SIZES, max_batch=512)
+    net.set_params(params)
+    lr = 1e-3
+    net.train(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev), 1, lr)
+    after = net.get_params()
+    _, go = M.loss_and_grads(params, X.astype(np.float64), T.astype(np.float64))
+    po, _ = M.adam_step(params, go, M.zero_state(params), 1, lr)
+    for (W, b), (W0, b0), (Wo, bo) in zip(after, params, po):
+        # the step itself: about lr per entry (Adam's first step is lr g / |g|)
+        assert _rel(W - W0, Wo - W0) <= 1e-2
+        assert _rel(b - b0, bo - b0) <= 1e-2
+    net.close()
+
+
+def test_training_converges_and_replays_are_deterministic(dev):
+    """Fit the reflection filters of a small synthetic set: the loss falls by
+    10x; 2 x 100 graph replays equal 200 replays bit for bit."""
+    import torch
+    h = H()
+    hs = synth.hrir_set(0, 5, 10)
+    n_dir = hs.n_filters // 2
+    X = M.features(hs.az, hs.el).astype(np.float32)
+    T = np.zeros((n_dir, SIZES[-1]), dtype=np.float32)
+    T[:, :hs.g.shape[1]] = hs.g[0::2]
+    T[:, 200:200 + hs.g.shape[1]] = hs.g[1::2]
+    x = torch.from_numpy(X).to(dev)
+    t = torch.from_numpy(T).to(dev)
+    init = synth.mlp_params(8, SIZES)
+    a, b = h.Mlp(SIZES, 64), h.Mlp(SIZES, 64)
+    a.set_params(init)
+    b.set_params(init)
+    l0, _ = a.grads(x, t)
+    a.train(x, t, 100, 1e-3)
+    la = a.train(x, t, 100, 1e-3)
+    lb = b.train(x, t, 200, 1e-3)
+    assert la == lb
+    for (Wa, ba), (Wb, bb) in zip(a.get_params(), b.get_params()):
+        np.testing.assert_array_equal(Wa, Wb)
+        np.testing.assert_array_equal(ba, bb)
+    assert la <= l0 / 10, (l0, la)
+    a.close()
+    b.close()
+
+
+def test_argument_errors(dev):
+    h = H()
+    with pytest.raises(h.HrirError):
+        h.Mlp([4], 10)
+    with pytest.raises(h.HrirError):
+        h.Mlp([4, 0, 3], 10)
+    net = h.Mlp([4, 8, 3], 10)
+    with pytest.raises(h.HrirError):
+        net.set_params([(np.zeros((4, 8)), np.zeros(8))])          # too few values
+    with pytest.raises(h.HrirError):
+        net.set_params([(np.full((4, 8), np.nan), np.zeros(8)), (np.zeros((8, 3)), np.zeros(3))])
+    net.close()
