@@ -421,6 +421,49 @@ int stream_info(const hrir_server* server, int64_t* info8);
 void stream_close(hrir_server* server);
 
 /* ------------------------------------------------------------------------
+ * Moving sources (Eq. (2) with the direction, i.e. the reflection filter,
+ * changing over time) and the device-side top-K that turns dense predicted
+ * reflection filters into plan rows.
+ *
+ * spconv_plan_topk  for each of n_rows rows of d_dense (device f32, row i at
+ *                   d_dense + i * row_stride), the plan's k largest finite
+ *                   positive entries among the first `width` (<= lg), ties to
+ *                   the lower position, in ascending position order, padded
+ *                   with (0, 0), are written to plan rows first_row + i.  The
+ *                   update is ordered on `stream`: renders that use those rows
+ *                   must follow it on that stream (or wait for it).
+ * spconv_plan_read  copies plan rows [first_row, first_row + n_rows) back to
+ *                   host i32 / f32 [n_rows][k] (waits for the device).
+ * moving_create     n_src sources of src_len samples each, contiguous in
+ *                   the source buffer (source i at i * src_len); the direction
+ *                   changes every seg_len samples (a multiple of 256);
+ *                   n_seg = ceil(src_len / seg_len).  Output sample t of an
+ *                   ear uses the filter of segment j = min(t / seg_len,
+ *                   n_seg - 1); in its first `fade` (0..256) samples, u =
+ *                   t - j seg_len < fade with j >= 1, the output is
+ *                   a y_j + (1 - a) y_{j-1}, a = (u + 1) / fade, y_j the render
+ *                   with segment j's filter.  The plan must outlive the object.
+ * moving_render     seg_filt host i32[n_src][n_seg][2] plan rows (left,
+ *                   right) per segment, validated and staged through pinned
+ *                   memory (double buffered).  d_out device f32: the row of
+ *                   (source i, ear e) at (2 i + e) * out_stride, out_stride >=
+ *                   src_len + lf + lg - 2.
+ * moving_info       host int64[4]: n_seg, output row length, tiles, tile length.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct hrir_moving hrir_moving;
+
+int spconv_plan_topk(hrir_plan* plan, int32_t first_row, const float* d_dense, int32_t n_rows, int64_t row_stride,
+                     int32_t width, void* stream);
+int spconv_plan_read(const hrir_plan* plan, int32_t first_row, int32_t n_rows, int32_t* p_out, float* g_out);
+int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_len, int32_t seg_len, int32_t fade,
+                  hrir_moving** out);
+int moving_render(hrir_moving* moving, const float* d_src, int64_t src_elems, const int32_t* seg_filt, float* d_out,
+                  int64_t out_stride, int64_t out_elems, void* stream);
+int moving_info(const hrir_moving* moving, int64_t* info4);
+void moving_destroy(hrir_moving* moving);
+
+/* ------------------------------------------------------------------------
  * Direction-conditioned surrogate: a ReLU MLP that predicts a direction's
  * reflection filters (the sparse non-negative factor of Eq. (1)) from
  * (sin az, cos az, sin el, cos el), trained on factorizations of the

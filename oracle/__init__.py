@@ -11,8 +11,10 @@ Sec. IV-F, which are one-line formulas.
 
 Parity status per routine (what pins each one is in ``tests/test_oracle_*``):
   conv_direct, conv_fft, conv_fft_ola, dense_render, sparse_render,
-  sparse_render_points, block_render, fstep, gstep, factorize (cost trace and
-  fixed-point properties), topk, nnls, refit, metrics, cost model -- pinned.
+  sparse_render_points, block_render, moving_render, fstep, gstep, factorize
+  (cost trace and fixed-point properties), topk, nnls, refit, metrics, cost
+  model -- pinned.  The paper's sparsifier is in ``oracle.l1`` and the
+  surrogate network in ``oracle.mlp``, each with its own pins.
   The exact f / G values of a factorization are not unique (positive scale,
   local minima); only properties and library-vs-oracle agreement from the same
   G0 pin them.
@@ -62,6 +64,8 @@ def _load():
         "or_dense_render_jobs": (c_int, [P_d, P_i64, P_i64, P_d, c_int64, P_i32, c_int64, P_d, P_i64]),
         "or_sparse_render_points": (None, [P_d, c_int64, P_d, c_int64, P_i32, P_d, c_int64,
                                            P_i64, c_int64, P_d]),
+        "or_moving_render": (c_int, [P_d, c_int64, P_d, c_int64, P_i32, P_d, c_int64, c_int64, P_i32, c_int64,
+                                     c_int64, P_d]),
         "or_block_render_step": (c_int, [P_d, c_int64, P_i32, P_d, c_int64, c_int64, P_d, P_d,
                                          P_d, c_int64, c_int, P_d]),
         "or_splitmix64": (None, [c_uint64, c_int64, P_u64]),
@@ -192,6 +196,19 @@ def sparse_render_points(r, s, p, g, t) -> np.ndarray:
     out = np.empty(t.size)
     _load().or_sparse_render_points(_p(r, c_double), r.size, _p(s, c_double), s.size, _p(p, c_int32),
                                     _p(g, c_double), p.size, _p(t, c_int64), t.size, _p(out, c_double))
+    return out
+
+
+def moving_render(r, src, p, g, lg: int, filt, seg: int, fade: int) -> np.ndarray:
+    """One ear of a moving source: filt[j] is segment j's row of the tap
+    table (p, g: [F][k]); see or_moving_render."""
+    r, src, p, g, filt = _d(r), _d(src), _i32(p), _d(g), _i32(filt)
+    n = src.size
+    assert filt.size == (n + seg - 1) // seg
+    out = np.empty(n + r.size + lg - 2)
+    _check(_load().or_moving_render(_p(r, c_double), r.size, _p(src, c_double), n, _p(p, c_int32), _p(g, c_double),
+                                    p.shape[1], lg, _p(filt, c_int32), seg, fade, _p(out, c_double)),
+           "moving_render")
     return out
 
 

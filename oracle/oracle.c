@@ -192,6 +192,47 @@ int or_sparse_render_jobs(const double* r, int64_t lf, const double* src, const 
     return rc;
 }
 
+/* One output sample of a sparse render: sum_q g[q] z[t - p[q]], z zero
+ * outside [0, nz). */
+static double tap_sum(const double* z, int64_t nz, const int32_t* p, const double* g, int64_t k, int64_t t) {
+    double acc = 0.0;
+    for (int64_t q = 0; q < k; ++q) {
+        const int64_t u = t - p[q];
+        if (u >= 0 && u < nz) acc += g[q] * z[u];
+    }
+    return acc;
+}
+
+/* Moving source, one ear: the reflection filter changes every seg samples
+ * (filt[j] is segment j's row of the tap table, n_seg = ceil(n / seg)).
+ * Output sample t uses segment j = min(t / seg, n_seg - 1); in the first
+ * fade samples of a segment j >= 1 (u = t - j seg < fade, t / seg = j) it is
+ * a y_j + (1 - a) y_{j-1} with a = (u + 1) / fade, y_j the render with
+ * segment j's filter.  z = r * s (Eq. (2)); out has n + lf + lg - 2 samples. */
+int or_moving_render(const double* r, int64_t lf, const double* src, int64_t n, const int32_t* p,
+                     const double* g, int64_t k, int64_t lg, const int32_t* filt, int64_t seg, int64_t fade,
+                     double* out) {
+    const int64_t nz = n + lf - 1, n_out = n + lf + lg - 2, n_seg = (n + seg - 1) / seg;
+    double* z = (double*)malloc((size_t)nz * sizeof(double));
+    if (!z) return OR_ENOMEM;
+    or_conv_direct(r, lf, src, n, z);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n_out; ++t) {
+        const int64_t jr = t / seg;
+        const int64_t j = jr < n_seg - 1 ? jr : n_seg - 1;
+        double y = tap_sum(z, nz, p + (int64_t)filt[j] * k, g + (int64_t)filt[j] * k, k, t);
+        const int64_t u = t - j * seg;
+        if (fade > 0 && j >= 1 && jr == j && u < fade) {
+            const double a = (double)(u + 1) / (double)fade;
+            const double y0 = tap_sum(z, nz, p + (int64_t)filt[j - 1] * k, g + (int64_t)filt[j - 1] * k, k, t);
+            y = a * y + (1.0 - a) * y0;
+        }
+        out[t] = y;
+    }
+    free(z);
+    return OR_OK;
+}
+
 /* Dense render over a job list (h: [F][m]), parallel over jobs. */
 int or_dense_render_jobs(const double* src, const int64_t* src_off, const int64_t* src_len,
                          const double* h, int64_t m, const int32_t* jobs, int64_t n_jobs,

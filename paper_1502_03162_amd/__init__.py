@@ -138,6 +138,12 @@ def _load() -> ctypes.CDLL:
         "hrir_sparsify": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, c_int32, P_d, P_d, c_int32, c_double, c_int32,
                                   P_i32, P_f, P_i32, P_d, P_d]),
         "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_double, P_d, P_d]),
+        "spconv_plan_topk": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p]),
+        "spconv_plan_read": (c_int, [c_void_p, c_int32, c_int32, P_i32, P_f]),
+        "moving_create": (c_int, [c_void_p, c_int32, c_int64, c_int32, c_int32, POINTER(c_void_p)]),
+        "moving_render": (c_int, [c_void_p, c_void_p, c_int64, P_i32, c_void_p, c_int64, c_int64, c_void_p]),
+        "moving_info": (c_int, [c_void_p, P_i64]),
+        "moving_destroy": (None, [c_void_p]),
         "mlp_create": (c_int, [P_i32, c_int32, c_int32, POINTER(c_void_p)]),
         "mlp_num_params": (c_int64, [c_void_p]),
         "mlp_set_params": (c_int, [c_void_p, P_f, c_int64]),
@@ -162,7 +168,8 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_des
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
             "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
             "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma",
-            "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
+            "spconv_plan_topk", "spconv_plan_read", "moving_create", "moving_render", "moving_info",
+            "moving_destroy", "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
             "mlp_train", "mlp_destroy")
 
 
@@ -690,6 +697,58 @@ class Mlp:
     def close(self):
         if getattr(self, "_h", None):
             _lib.mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
+            pass
+
+
+def plan_topk(plan: Plan, first_row: int, dense, width: int, stream=None):
+    """spconv_plan_topk: rows of a device tensor [n_rows][row_stride] -> the
+    plan's tap rows first_row.. (k largest finite positive entries among the
+    first `width`)."""
+    dp, _ = _f32(dense)
+    _check(_lib.spconv_plan_topk(plan.handle, int(first_row), dp, int(dense.shape[0]), int(dense.stride(0)),
+                                 int(width), c_void_p(_stream_handle(stream))))
+
+
+def plan_read(plan: Plan, first_row: int, n_rows: int):
+    """Plan rows back to the host: (p int32 [n][k], g float32 [n][k])."""
+    p = np.empty((n_rows, plan.k), dtype=np.int32)
+    g = np.empty((n_rows, plan.k), dtype=np.float32)
+    _check(_lib.spconv_plan_read(plan.handle, int(first_row), int(n_rows), _ptr(p, c_int32), _ptr(g, c_float)))
+    return p, g
+
+
+class Moving:
+    """Moving sources (moving_*): n_src equal-length sources whose direction
+    changes every seg_len samples, with a linear crossfade of `fade` samples."""
+
+    def __init__(self, plan: Plan, n_src: int, src_len: int, seg_len: int, fade: int):
+        self.plan = plan
+        hd = c_void_p()
+        _check(_lib.moving_create(plan.handle, int(n_src), int(src_len), int(seg_len), int(fade), byref(hd)))
+        self._h = hd
+        v = np.zeros(4, dtype=np.int64)
+        _check(_lib.moving_info(hd, _ptr(v, c_int64)))
+        self.n_seg, self.out_len, self.n_tiles, self.tile = (int(x) for x in v)
+        self.n_src = n_src
+
+    def render(self, src, seg_filt, out, out_stride: int, stream=None):
+        sf = np.ascontiguousarray(seg_filt, dtype=np.int32)
+        if sf.shape != (self.n_src, self.n_seg, 2):
+            raise ValueError(f"seg_filt must be [{self.n_src}][{self.n_seg}][2]")
+        sp, sn = _f32(src)
+        op, on = _f32(out)
+        _check(_lib.moving_render(self._h, sp, sn, _ptr(sf, c_int32), op, int(out_stride), on,
+                                  c_void_p(_stream_handle(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.moving_destroy(self._h)
             self._h = None
 
     def __del__(self):

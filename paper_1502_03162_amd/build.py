@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
-SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "block.hip", "mlp.hip",
+SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "block.hip", "render_moving.hip", "mlp.hip",
            "autotune.cpp", "server.cpp", "loadgen.cpp", "factorize.cpp", "sparsify.cpp", "errors.cpp"]
 
 # Per-file extra flags.  The register-window kernel dispatches taps through a

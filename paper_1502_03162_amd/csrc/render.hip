@@ -360,6 +360,12 @@ extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const f
     return HRIR_OK;
 }
 
+namespace hrir {
+PlanView plan_view(const hrir_plan* pl) {
+    return PlanView{pl->lf, pl->lfp, pl->k, pl->kp, pl->lg, pl->n_filters, pl->device, pl->d_r, pl->d_p, pl->d_g};
+}
+}  // namespace hrir
+
 extern "C" int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3) {
     clear_error();
     if (!plan || !lf_k_lg3) return fail(HRIR_EINVAL, "spconv_plan_shape: null pointer");
@@ -379,6 +385,30 @@ extern "C" int spconv_plan_device(const hrir_plan* plan, const float** r, const 
     lfp_kp_nf3[0] = plan->lfp;
     lfp_kp_nf3[1] = plan->kp;
     lfp_kp_nf3[2] = plan->n_filters;
+    return HRIR_OK;
+}
+
+extern "C" int spconv_plan_read(const hrir_plan* plan, int32_t first_row, int32_t n_rows, int32_t* p_out,
+                                float* g_out) {
+    clear_error();
+    if (!plan || (n_rows > 0 && (!p_out || !g_out))) return fail(HRIR_EINVAL, "spconv_plan_read: null pointer");
+    if (first_row < 0 || n_rows < 0 || (int64_t)first_row + n_rows > plan->n_filters)
+        return fail(HRIR_EINVAL, "spconv_plan_read: rows outside the plan");
+    std::vector<int> hp((size_t)n_rows * plan->kp);
+    std::vector<float> hg((size_t)n_rows * plan->kp);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && n_rows > 0)
+        e = hipMemcpy(hp.data(), plan->d_p + (size_t)first_row * plan->kp, hp.size() * sizeof(int),
+                      hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n_rows > 0)
+        e = hipMemcpy(hg.data(), plan->d_g + (size_t)first_row * plan->kp, hg.size() * sizeof(float),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HRIR_EDEVICE, "spconv_plan_read: %s", hipGetErrorString(e));
+    for (int i = 0; i < n_rows; ++i)
+        for (int j = 0; j < plan->k; ++j) {
+            p_out[(size_t)i * plan->k + j] = hp[(size_t)i * plan->kp + j];
+            g_out[(size_t)i * plan->k + j] = hg[(size_t)i * plan->kp + j];
+        }
     return HRIR_OK;
 }
 

@@ -168,4 +168,16 @@ int quad_launch(int lfp, int kp, bool persistent, int grid, size_t lds_bytes, hi
                 const float* Gv, float* out, int lg, int TB, int* ctr);
 constexpr int kQuadTileMax = 4096;
 
+// Shape and device tables of a plan (render.hip owns the struct).
+struct PlanView {
+    int lf, lfp, k, kp, lg, n_filters, device;
+    float* d_r;
+    int* d_p;
+    float* d_g;
+};
+}  // namespace hrir
+struct hrir_plan;
+namespace hrir {
+PlanView plan_view(const hrir_plan* plan);
+
 }  // namespace hrir

@@ -1,0 +1,100 @@
+// The z tile of the quad LDS-gather kernels (render_quad.hip,
+// render_moving.hip): the source window is staged in LDS, the resonance FIR
+// forms z in registers, and z is written back as four copies shifted by
+// 0..3 samples, Zc[m] = z[t0 - H + m + c], so that every tap of every quad of
+// outputs is one aligned 16-byte LDS read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "render_common.h"
+
+namespace hrir {
+
+constexpr int kQR = 16;               // outputs per lane per chunk (4 quads)
+constexpr int kQChunk = 64 * kQR;     // outputs per wave per chunk
+constexpr int kQThreads = 512;        // 8 wave64 per workgroup
+constexpr int kQWaves = kQThreads / 64;
+constexpr int kQPass = 2;             // FIR passes of 8 z values per thread (8192 z: tiles up to 4096)
+static_assert(kQChunk == 1024, "quad chunk");
+static_assert(kQPass * kQThreads * kZpt >= kQuadTileMax + 2048 + 3, "FIR passes cover the largest tile");
+
+// Floats per shifted copy: holds m < TB + H (+ padding so that the copies
+// start on different banks).
+__host__ __device__ inline int quad_cs(int TB, int H) { return round_up(TB + H + 4, 8) + 4; }
+
+__host__ __device__ inline int lds_quad_len(int TB, int lg, int lfp) {
+    const int H = lg - 1;
+    const int s_len = round_up(TB + H + 3, kZpt) + lfp + 4;
+    const int c_len = 4 * quad_cs(TB, H);
+    return s_len > c_len ? s_len : c_len;
+}
+
+// Stages the tile's source, runs the FIR and writes the four shifted copies
+// of z into lds (ends with a barrier).  H = lg - 1; CS = quad_cs(TB, H).
+template <int LFP>
+__device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __restrict__ src,
+                                           const float* __restrict__ r, int lg, int TB, float* lds) {
+    const int tid = threadIdx.x;
+    const int H = lg - 1;
+    const int NZ = TB + H + 3;                 // z_win[u], u < NZ, covers every quad read
+    const int nz8 = round_up(NZ, kZpt);
+    const int CS = quad_cs(TB, H);
+    float* s_win = lds;
+    float* zc = lds;                           // the copies overwrite s_win after the FIR
+
+    stage_s<LFP, kQThreads>(td, src, H, nz8, s_win);
+
+    // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)
+    float rr[LFP];
+#pragma unroll
+    for (int n = 0; n < LFP; ++n) rr[n] = r[n];
+    float zz[kQPass][kZpt];
+#pragma unroll
+    for (int ps = 0; ps < kQPass; ++ps) {
+        const int u0 = (ps * kQThreads + tid) * kZpt;
+        if (u0 < nz8) {
+            float w[LFP + kZpt];
+#pragma unroll
+            for (int i = 0; i < LFP + kZpt; i += 4) {
+                const float4 v = *reinterpret_cast<const float4*>(s_win + u0 + i);
+                w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
+            }
+#pragma unroll
+            for (int a = 0; a < kZpt; ++a) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int n = 0; n < LFP; ++n) acc = fmaf(rr[n], w[a + LFP - 1 - n], acc);
+                zz[ps][a] = acc;
+            }
+        }
+    }
+    __syncthreads();                            // every read of s_win is done
+    // Zc[m] = z_win[m + c] for m < TB + H; interior groups of 8 without tests
+    const int mlim = TB + H;
+#pragma unroll
+    for (int ps = 0; ps < kQPass; ++ps) {
+        const int u0 = (ps * kQThreads + tid) * kZpt;
+        if (u0 >= 4 && u0 + kZpt <= mlim) {
+            float* z0 = zc + u0;
+            *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);
+            *reinterpret_cast<float4*>(z0 + 4) = make_float4(zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c)
+#pragma unroll
+                for (int a = 0; a < kZpt; ++a) zc[c * CS + u0 + a - c] = zz[ps][a];
+        } else if (u0 < nz8) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int a = 0; a < kZpt; ++a) {
+                    const int m = u0 + a - c;
+                    if (m >= 0 && m < mlim) zc[c * CS + m] = zz[ps][a];
+                }
+        }
+    }
+    __syncthreads();
+
+}
+
+}  // namespace hrir

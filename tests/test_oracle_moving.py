@@ -1,0 +1,49 @@
+"""Pins of the oracle's moving-source render against static renders of the
+same source (Eq. (2) with one reflection filter), which are pinned
+themselves: one filter for every segment reproduces the static render; with
+no fade each segment's samples equal the static render with that segment's
+filter; inside a fade the output is the stated linear blend of the two
+static renders."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+LF, LG, K, F = 11, 40, 6, 7
+
+
+def _setup(seed, n):
+    rng = np.random.default_rng(seed)
+    r = rng.standard_normal(LF)
+    p, g = synth.random_taps(seed + 1, F, K, LG, nnz_min=2)
+    s = synth.white(seed + 2, n).astype(np.float64)
+    return r, p, g.astype(np.float64), s, rng
+
+
+@pytest.mark.parametrize("n,seg,fade", [(1000, 256, 64), (1024, 256, 0), (700, 512, 256), (3, 256, 64)])
+def test_one_filter_everywhere_is_the_static_render(n, seg, fade):
+    r, p, g, s, _ = _setup(n, n)
+    filt = np.full((n + seg - 1) // seg, 4, dtype=np.int32)
+    y = oracle.moving_render(r, s, p, g, LG, filt, seg, fade)
+    ref = oracle.sparse_render(r, s, p[4], g[4], LG)
+    assert y.shape == ref.shape
+    assert np.max(np.abs(y - ref)) <= 1e-13 * max(np.max(np.abs(ref)), 1e-300)
+
+
+@pytest.mark.parametrize("n,seg,fade", [(2000, 256, 0), (2000, 256, 64), (1800, 512, 100)])
+def test_segments_and_fades_follow_the_static_renders(n, seg, fade):
+    r, p, g, s, rng = _setup(7 + n + fade, n)
+    n_seg = (n + seg - 1) // seg
+    filt = rng.integers(0, F, n_seg).astype(np.int32)
+    y = oracle.moving_render(r, s, p, g, LG, filt, seg, fade)
+    stat = {f: oracle.sparse_render(r, s, p[f], g[f], LG) for f in set(filt.tolist())}
+    for t in range(y.size):
+        jr = t // seg
+        j = min(jr, n_seg - 1)
+        want = stat[filt[j]][t]
+        u = t - j * seg
+        if fade > 0 and j >= 1 and jr == j and u < fade:
+            a = (u + 1) / fade
+            want = a * want + (1 - a) * stat[filt[j - 1]][t]
+        assert abs(y[t] - want) <= 1e-12 * (1 + abs(want)), t
