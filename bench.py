@@ -325,6 +325,133 @@ def bench_sparsifier(H, hs, fac, lf, lg, k):
     return res
 
 
+def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
+    """Direction-conditioned surrogate: an MLP (sin az, cos az, sin el, cos el)
+    -> 4 x 256 -> 2 x 200 dense reflection taps, trained on the dense
+    factorization G of 1,000 of the 1,250 directions; the 250 held out are
+    judged against their own factorization (top-16 of the prediction against
+    the factorization's 16-tap filter).  Then 128 moving sources of 262,144
+    samples whose direction changes every 512 samples (64-sample crossfade):
+    every segment's direction goes through the network on the GPU, top-16
+    into plan rows, and the fallback rule (nearest held-out direction worse
+    than -30 dB -> nearest measured filter) picks predicted or measured rows."""
+    import synth
+    D = hs.az.size
+    G = fac["G"]
+    T = np.zeros((D, 400), np.float32)
+    T[:, :lg] = G[0::2]
+    T[:, 200:200 + lg] = G[1::2]
+
+    def feats(az, el):
+        return np.stack([np.sin(az), np.cos(az), np.sin(el), np.cos(el)], axis=-1).astype(np.float32)
+
+    X = feats(hs.az, hs.el)
+    perm = np.random.default_rng(31).permutation(D)
+    tr, va = np.sort(perm[:1000]), np.sort(perm[1000:])
+    sizes = [4, 256, 256, 256, 256, 400]
+    n_src, N, seg, fade = 128, 262144, 512, 64
+    n_seg = N // seg
+    net = H.Mlp(sizes, max_batch=n_src * n_seg)
+    net.set_params(synth.mlp_params(5, sizes))
+    x_tr = torch.from_numpy(X[tr]).to(dev)
+    t_tr = torch.from_numpy(T[tr]).to(dev)
+    t0 = time.perf_counter()
+    losses = []
+    for chunk in range(args.surrogate_steps // 1000):
+        losses.append(net.train(x_tr, t_tr, 1000, 1e-3))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"surrogate: {args.surrogate_steps} Adam steps in {train_s:.2f} s, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+
+    # held-out quality: top-16 of the prediction vs the factorization's filter
+    K = fac["p"].shape[1]
+    n_meas = 2 * D
+    y_va = torch.empty((va.size, 400), device=dev)
+    net.forward(torch.from_numpy(X[va]).to(dev), y_va)
+    plan_v = H.Plan(r, np.concatenate([fac["p"], np.zeros((2 * va.size, K), np.int32)]),
+                    np.concatenate([fac["g"], np.zeros((2 * va.size, K), np.float32)]), lg)
+    H.plan_topk(plan_v, n_meas, y_va.view(2 * va.size, 200), lg)
+    pp, gg = H.plan_read(plan_v, n_meas, 2 * va.size)
+    plan_v.close()
+    f64 = fac["f"]
+
+    def dense(p, g):
+        out = np.zeros(lg)
+        np.add.at(out, p, g.astype(np.float64))
+        return out
+
+    e_fact = np.zeros((va.size, 2))
+    e_nn = np.zeros((va.size, 2))
+
+    def unit(a, e):
+        return np.stack([np.sin(a), np.cos(a) * np.cos(e), np.cos(a) * np.sin(e)], axis=-1)
+
+    Ut = unit(hs.az[tr], hs.el[tr])
+    for i, v in enumerate(va):
+        m = tr[int(np.argmax(Ut @ unit(hs.az[v], hs.el[v])))]
+        for e in range(2):
+            ref = np.convolve(f64, dense(fac["p"][2 * v + e], fac["g"][2 * v + e]))
+            pred = np.convolve(f64, dense(pp[2 * i + e], gg[2 * i + e]))
+            near = np.convolve(f64, dense(fac["p"][2 * m + e], fac["g"][2 * m + e]))
+            e_fact[i, e] = 10 * np.log10(np.sum((pred - ref) ** 2) / np.sum(ref ** 2))
+            e_nn[i, e] = 10 * np.log10(np.sum((near - ref) ** 2) / np.sum(ref ** 2))
+    val_err = e_fact.max(axis=1)
+    log(f"surrogate held-out E_dB vs factorization: median {np.median(e_fact):.2f}, "
+        f"nearest measured filter {np.median(e_nn):.2f}")
+
+    # moving sources: smooth trajectories through the measured range
+    rng = np.random.default_rng(77)
+    tt = (np.arange(n_seg) + 0.5) / n_seg
+    az0, el0 = rng.uniform(-1.2, 1.2, n_src), rng.uniform(-0.7, 3.8, n_src)
+    q_az = np.clip(az0[:, None] + 0.3 * np.sin(2 * np.pi * (tt[None] * rng.uniform(0.5, 2, (n_src, 1)))), -1.39, 1.39)
+    q_el = el0[:, None] + rng.uniform(-1.5, 1.5, (n_src, 1)) * tt[None]
+    q_az, q_el = q_az.reshape(-1), q_el.reshape(-1)
+    nq = q_az.size
+    xq = torch.from_numpy(feats(q_az, q_el)).to(dev)
+    yq = torch.empty((nq, 400), device=dev)
+    p_all = np.concatenate([fac["p"], np.zeros((2 * nq, K), np.int32)])
+    g_all = np.concatenate([fac["g"], np.zeros((2 * nq, K), np.float32)])
+    plan = H.Plan(r, p_all, g_all, lg)
+
+    def infer():
+        net.forward(xq, yq)
+        H.plan_topk(plan, n_meas, yq.view(2 * nq, 200), lg)
+
+    inf_ms, _ = time_launches(infer, 5, 1)
+    choice = H.surrogate_select(q_az, q_el, hs.az[va], hs.el[va], val_err, hs.az, hs.el, -30.0)
+    q = np.arange(nq)
+    rows = np.where(choice[:, None] < 0, n_meas + 2 * q[:, None] + np.arange(2)[None],
+                    2 * np.maximum(choice, 0)[:, None] + np.arange(2)[None]).astype(np.int32)
+    seg_filt = rows.reshape(n_src, n_seg, 2)
+    srcs = np.concatenate([synth.pink(900 + i, N) for i in range(n_src)])
+    src = torch.from_numpy(srcs).to(dev)
+    mv = H.Moving(plan, n_src, N, seg, fade)
+    stride = (mv.out_len + 63) // 64 * 64
+    out = torch.empty(2 * n_src * stride, device=dev)
+    mms, _ = time_launches(lambda: mv.render(src, seg_filt, out, stride), args.steps, args.warmup)
+    n_out = 2 * n_src * mv.out_len
+    alg = 4.0 * n_out + 4.0 * n_src * N
+    res = {"workload": "MLP 4 -> 4 x 256 -> 400 (301,456 parameters), FP32 weights, bf16 activations; "
+                       "trained on 1,000 of 1,250 directions, 250 held out; 128 moving sources x 262,144 samples, "
+                       "direction every 512 samples, 64-sample crossfade, K = 16",
+           "params": net.n_params, "train_steps": args.surrogate_steps, "train_s": train_s,
+           "loss_first": losses[0], "loss_last": losses[-1],
+           "heldout_E_dB_vs_factorization": {"median": float(np.median(e_fact)), "mean": float(np.mean(e_fact)),
+                                             "worst": float(np.max(e_fact)),
+                                             "frac_below_-30": float(np.mean(e_fact < -30))},
+           "nearest_measured_E_dB": {"median": float(np.median(e_nn)), "mean": float(np.mean(e_nn))},
+           "fallback_fraction": float(np.mean(choice >= 0)),
+           "inference": {"queries": nq, "ms": inf_ms, "queries_per_s": nq / (inf_ms * 1e-3)},
+           "moving_render": {"ms_per_step": mms, "output_samples_per_s": n_out / (mms * 1e-3),
+                             "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "kernel": "k_render_moving<32,16>"}}
+    log(f"surrogate inference: {nq} directions in {inf_ms:.3f} ms; fallback {100 * np.mean(choice >= 0):.1f} %; "
+        f"moving render {mms:.3f} ms, {n_out / (mms * 1e-3):.3g} samples/s")
+    mv.close()
+    plan.close()
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +476,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds per streaming-loop load level (0: skip)")
     ap.add_argument("--no-sparsifier", action="store_true", help="skip the L1-NNLS sparsifier quality section")
+    ap.add_argument("--surrogate-steps", type=int, default=12000,
+                    help="Adam steps of the surrogate network (multiple of 1000; 0: skip the section)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run 3 device copies of 1 GiB (read 1 GiB + write 1 GiB each) to calibrate counters")
     args = ap.parse_args()
@@ -467,6 +596,7 @@ def main():
     latency = bench_latency(H, torch, dev, fac, r, lg, args) if args.latency_ticks > 0 else None
     serving = bench_serving(H, fac, r, lg, args) if args.serve_seconds > 0 else None
     sparsifier = None if args.no_sparsifier else bench_sparsifier(H, hs, fac, lf, lg, args.k)
+    surrogate = bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args) if args.surrogate_steps > 0 else None
 
     res = {
         "metric": METRIC,
@@ -500,6 +630,7 @@ def main():
         "uneven": uneven,
         "block_latency": latency,
         "serving": serving,
+        "surrogate": surrogate,
         "wall_s_timed": wall,
     }
     del out

@@ -464,12 +464,13 @@ int moving_info(const hrir_moving* moving, int64_t* info4);
 void moving_destroy(hrir_moving* moving);
 
 /* ------------------------------------------------------------------------
- * Direction-conditioned surrogate: a ReLU MLP that predicts a direction's
+ * Direction-conditioned surrogate: an MLP that predicts a direction's dense
  * reflection filters (the sparse non-negative factor of Eq. (1)) from
  * (sin az, cos az, sin el, cos el), trained on factorizations of the
  * measured directions (Alg. 1) so that directions between them get filters
- * too.  Layer l maps sizes[l] -> sizes[l + 1] with ReLU (the output layer
- * too, so taps are non-negative).  FP32 master weights; activations are
+ * too.  Layer l maps sizes[l] -> sizes[l + 1], ReLU on every layer but the
+ * last, which is linear; the taps are its largest positive outputs
+ * (spconv_plan_topk), hence non-negative.  FP32 master weights; activations are
  * stored as bfloat16 between layers (inputs included, round to nearest
  * even); products accumulate in FP32 on MFMA; loss = mean squared error
  * over all outputs; Adam (beta 0.9 / 0.999, eps 1e-8) with bias correction.
@@ -494,6 +495,17 @@ void moving_destroy(hrir_moving* moving);
  * Device buffers belong to the caller and must stay valid until the stream
  * reaches the work.  Errors: EINVAL, ENOMEM, EDEVICE.
  * ---------------------------------------------------------------------- */
+/* surrogate_select: the fallback rule for directions the surrogate predicts.
+ * For each query direction (radians, the grid's interaural-polar angles:
+ * lateral az, polar el), the nearest validation direction by the angle
+ * between unit vectors (sin az, cos az cos el, cos az sin el) decides: if
+ * the surrogate's error measured there, val_err_db, exceeds max_err_db, the
+ * query takes the nearest measured direction (choice = its index), else the
+ * surrogate (choice = -1).  Ties go to the lower index.  Host, synchronous. */
+int surrogate_select(const double* q_az, const double* q_el, int32_t n_q, const double* val_az, const double* val_el,
+                     const double* val_err_db, int32_t n_val, const double* meas_az, const double* meas_el,
+                     int32_t n_meas, double max_err_db, int32_t* choice);
+
 typedef struct hrir_mlp hrir_mlp;
 
 int mlp_create(const int32_t* sizes, int32_t n_layers, int32_t max_batch, hrir_mlp** out);

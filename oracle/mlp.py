@@ -3,7 +3,8 @@
 Only the tests and the benchmark may import this module; it shares no code
 with the GPU library.  The surrogate predicts a direction's reflection
 filters (the sparse factor of Eq. (1)) from (sin az, cos az, sin el, cos el)
-through ReLU layers; activations are stored as bfloat16 between layers, so
+through ReLU hidden layers and a linear output layer (the taps are the
+largest positive outputs); activations are stored as bfloat16 between layers, so
 the oracle rounds at the same points (round to nearest, ties to even, on the
 FP64 value) and computes everything else in FP64.
 
@@ -46,8 +47,8 @@ def forward(params, X, rounding: bool = True):
     for li, (W, b) in enumerate(params):
         z = h @ W + b
         cache.append((h, z))
-        a = np.maximum(z, 0.0)
-        h = rnd(a) if li + 1 < len(params) else a      # the output stays wide
+        last = li + 1 == len(params)
+        h = z if last else rnd(np.maximum(z, 0.0))     # ReLU hidden layers, linear output
     return h, cache
 
 
@@ -62,7 +63,7 @@ def loss_and_grads(params, X, T, rounding: bool = True):
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]
         h_in, z = cache[li]
-        dz = dh * (z > 0)
+        dz = dh if li + 1 == len(params) else dh * (z > 0)
         grads[li] = (h_in.T @ dz, dz.sum(axis=0))
         dh = dz @ W.T
     return loss, grads

@@ -144,6 +144,7 @@ def _load() -> ctypes.CDLL:
         "moving_render": (c_int, [c_void_p, c_void_p, c_int64, P_i32, c_void_p, c_int64, c_int64, c_void_p]),
         "moving_info": (c_int, [c_void_p, P_i64]),
         "moving_destroy": (None, [c_void_p]),
+        "surrogate_select": (c_int, [P_d, P_d, c_int32, P_d, P_d, P_d, c_int32, P_d, P_d, c_int32, c_double, P_i32]),
         "mlp_create": (c_int, [P_i32, c_int32, c_int32, POINTER(c_void_p)]),
         "mlp_num_params": (c_int64, [c_void_p]),
         "mlp_set_params": (c_int, [c_void_p, P_f, c_int64]),
@@ -169,7 +170,7 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_des
             "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
             "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma",
             "spconv_plan_topk", "spconv_plan_read", "moving_create", "moving_render", "moving_info",
-            "moving_destroy", "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
+            "moving_destroy", "surrogate_select", "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
             "mlp_train", "mlp_destroy")
 
 
@@ -704,6 +705,18 @@ class Mlp:
             self.close()
         except Exception:  # noqa: BLE001  (interpreter shutdown: the library may already be gone)
             pass
+
+
+def surrogate_select(q_az, q_el, val_az, val_el, val_err_db, meas_az, meas_el, max_err_db: float = -30.0):
+    """Per query: -1 (use the surrogate) or the index of the nearest measured
+    direction (surrogate_select)."""
+    d = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+    qa, qe, va, ve, vr, ma, me = (d(x) for x in (q_az, q_el, val_az, val_el, val_err_db, meas_az, meas_el))
+    ch = np.empty(qa.size, dtype=np.int32)
+    _check(_lib.surrogate_select(_ptr(qa, c_double), _ptr(qe, c_double), qa.size, _ptr(va, c_double),
+                                 _ptr(ve, c_double), _ptr(vr, c_double), va.size, _ptr(ma, c_double),
+                                 _ptr(me, c_double), ma.size, float(max_err_db), _ptr(ch, c_int32)))
+    return ch
 
 
 def plan_topk(plan: Plan, first_row: int, dense, width: int, stream=None):

@@ -1,7 +1,11 @@
-// Direction-conditioned surrogate of the reflection filters: a ReLU MLP from
-// (sin az, cos az, sin el, cos el) to a direction's reflection taps, trained
-// on the factorizations the method produces (Alg. 1), so that filters for
-// directions between the measured ones come from the model.
+// Direction-conditioned surrogate of the reflection filters: an MLP with ReLU
+// hidden layers and a linear output layer from (sin az, cos az, sin el,
+// cos el) to a direction's dense reflection filters, trained on the
+// factorizations the method produces (Alg. 1), so that filters for
+// directions between the measured ones come from the model.  Taps are the
+// largest positive outputs (spconv_plan_topk), so they are non-negative as
+// Eq. (1) requires; a ReLU on the output layer would instead leave output
+// units that never recover from zero.
 //
 // Precision: FP32 master weights, bfloat16 activations between layers (round
 // to nearest even), FP32 accumulation.  The contractions run on MFMA
@@ -51,22 +55,41 @@ struct Epi {
     int64_t out_ld;
 };
 
+__device__ __forceinline__ void epilogue(const Epi& e, int i, int j, float x) {
+    if (e.bias) x += e.bias[j];
+    if (e.relu) x = fmaxf(x, 0.0f);
+    if (e.mask && !(bf16_to_f32(e.mask[(int64_t)i * e.mask_ld + j]) > 0.0f)) x = 0.0f;
+    if (e.out_bf16)
+        static_cast<uint16_t*>(e.out)[(int64_t)i * e.out_ld + j] = f32_to_bf16(x);
+    else
+        static_cast<float*>(e.out)[(int64_t)i * e.out_ld + j] = x;
+}
+
 // C[M][N] = A[M][K] B[K][N]; A(i, k) = A[i sa_r + k sa_c], B(k, j) = B[k sb_r + j sb_c].
-// 256 threads: four waves, each one 32 x 32 output tile of MFMA 32x32x2.
+// One wave per 32 x 32 output tile (MFMA 32x32x2).  With gridDim.z > 1 the
+// contraction is split: block z sums k in [z k_chunk, (z + 1) k_chunk) and
+// writes its raw partial tile to ws[z][M][N]; k_splitk_reduce adds the parts
+// in order and applies the epilogue.
 template <class TA>
-__global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, int64_t sa_r, int64_t sa_c,
-                                              const float* __restrict__ B, int64_t sb_r, int64_t sb_c, int M,
-                                              int N, int K, Epi e) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row0 = blockIdx.y * 64 + 32 * (wave & 1);
-    const int col0 = blockIdx.x * 64 + 32 * (wave >> 1);
+__global__ __launch_bounds__(64) void k_gemm(const TA* __restrict__ A, int64_t sa_r, int64_t sa_c,
+                                             const float* __restrict__ B, int64_t sb_r, int64_t sb_c, int M, int N,
+                                             int K, int k_chunk, Epi e, float* __restrict__ ws) {
+    const int lane = threadIdx.x;
+    const int row0 = blockIdx.y * 32, col0 = blockIdx.x * 32;
     const int ai = row0 + (lane & 31), bj = col0 + (lane & 31), kk = lane >> 5;
+    const int kb = blockIdx.z * k_chunk, ke = min(K, kb + k_chunk);
     f32x16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += 2) {
-        const int k = k0 + kk;
-        const float a = (ai < M && k < K) ? load_elt<TA>(A, (int64_t)ai * sa_r + (int64_t)k * sa_c) : 0.0f;
-        const float b = (bj < N && k < K) ? B[(int64_t)k * sb_r + (int64_t)bj * sb_c] : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    // eight k-steps per iteration: their loads are issued together, then the MFMAs
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        float a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + 2 * u + kk;
+            a[u] = (ai < M && k < ke) ? load_elt<TA>(A, (int64_t)ai * sa_r + (int64_t)k * sa_c) : 0.0f;
+            b[u] = (bj < N && k < ke) ? B[(int64_t)k * sb_r + (int64_t)bj * sb_c] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
     }
     // accumulator v of lane l holds C[row0 + (v & 3) + 4 (l >> 5) + 8 (v >> 2)][col0 + (l & 31)]
 #pragma unroll
@@ -74,14 +97,19 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, int64_t 
         const int i = row0 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
         const int j = col0 + (lane & 31);
         if (i >= M || j >= N) continue;
-        float x = acc[v];
-        if (e.bias) x += e.bias[j];
-        if (e.relu) x = fmaxf(x, 0.0f);
-        if (e.mask && !(bf16_to_f32(e.mask[(int64_t)i * e.mask_ld + j]) > 0.0f)) x = 0.0f;
-        if (e.out_bf16)
-            static_cast<uint16_t*>(e.out)[(int64_t)i * e.out_ld + j] = f32_to_bf16(x);
+        if (gridDim.z > 1)
+            ws[((int64_t)blockIdx.z * M + i) * N + j] = acc[v];
         else
-            static_cast<float*>(e.out)[(int64_t)i * e.out_ld + j] = x;
+            epilogue(e, i, j, acc[v]);
+    }
+}
+
+__global__ void k_splitk_reduce(const float* __restrict__ ws, int splits, int M, int N, Epi e) {
+    const int64_t total = (int64_t)M * N;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int z = 0; z < splits; ++z) s += ws[z * total + q];
+        epilogue(e, (int)(q / N), (int)(q % N), s);
     }
 }
 
@@ -90,7 +118,8 @@ __global__ void k_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __re
         y[i] = f32_to_bf16(x[i]);
 }
 
-// dz = scale (y - t) [y > 0]; per-block partial sums of (y - t)^2 in fixed order.
+// dz = scale (y - t) (the output layer is linear); per-block partial sums of
+// (y - t)^2 in fixed order.
 constexpr int kLossThreads = 256;
 __global__ __launch_bounds__(kLossThreads) void k_loss_grad(const float* __restrict__ y, const float* __restrict__ t,
                                                             int64_t n, float scale, float* __restrict__ dz,
@@ -100,7 +129,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_grad(const float* __restr
     for (int64_t i = blockIdx.x * (int64_t)kLossThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kLossThreads) {
         const float d = y[i] - t[i];
         s += (double)d * d;
-        dz[i] = y[i] > 0.0f ? scale * d : 0.0f;
+        dz[i] = scale * d;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -157,6 +186,8 @@ struct hrir_mlp {
     std::vector<uint16_t*> d_act;           // bf16 [max_batch][sizes[l]], l < L
     float* d_out = nullptr;                 // fp32 [max_batch][sizes[L]]
     float* d_dz[2] = {nullptr, nullptr};    // fp32 gradients of pre-activations (ping-pong)
+    float* d_ws = nullptr;                  // split-K partial tiles
+    int64_t ws_elems = 0;
     int* d_step = nullptr;
     double* d_part = nullptr;               // loss partial sums
     int n_part = 0;
@@ -176,22 +207,38 @@ void free_mlp(hrir_mlp* m) {
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
     if (m->cap) (void)hipStreamDestroy(m->cap);
-    for (float* p : {m->d_p, m->d_g, m->d_m, m->d_v, m->d_out, m->d_dz[0], m->d_dz[1]}) (void)hipFree(p);
+    for (float* p : {m->d_p, m->d_g, m->d_m, m->d_v, m->d_out, m->d_dz[0], m->d_dz[1], m->d_ws}) (void)hipFree(p);
     for (uint16_t* p : m->d_act) (void)hipFree(p);
     (void)hipFree(m->d_step);
     (void)hipFree(m->d_part);
     delete m;
 }
 
-hipError_t gemm(hipStream_t st, bool a_bf16, const void* A, int64_t sa_r, int64_t sa_c, const float* B, int64_t sb_r,
-                int64_t sb_c, int M, int N, int K, const Epi& e) {
-    const dim3 grid(cdiv(N, 64), cdiv(M, 64));
+constexpr int kMaxSplits = 16;
+
+// Launches C = A B with the epilogue; contractions much longer than the
+// output is wide (the weight gradients, over the batch) are split over up
+// to kMaxSplits blocks when the workspace holds the partial tiles.
+hipError_t gemm(hrir_mlp* m, hipStream_t st, bool a_bf16, const void* A, int64_t sa_r, int64_t sa_c, const float* B,
+                int64_t sb_r, int64_t sb_c, int M, int N, int K, const Epi& e) {
+    const int tiles = cdiv(M, 32) * cdiv(N, 32);
+    int splits = 1;
+    if (tiles < 512 && K >= 256) {
+        splits = std::min<int>(kMaxSplits, std::max(1, K / 128));
+        while (splits > 1 && (int64_t)splits * M * N > m->ws_elems) --splits;
+    }
+    const int k_chunk = (cdiv(K, splits) + 15) / 16 * 16;
+    splits = cdiv(K, k_chunk);
+    const dim3 grid(cdiv(N, 32), cdiv(M, 32), splits);
     if (a_bf16)
-        hipLaunchKernelGGL(k_gemm<uint16_t>, grid, dim3(256), 0, st, static_cast<const uint16_t*>(A), sa_r, sa_c, B,
-                           sb_r, sb_c, M, N, K, e);
+        hipLaunchKernelGGL(k_gemm<uint16_t>, grid, dim3(64), 0, st, static_cast<const uint16_t*>(A), sa_r, sa_c, B,
+                           sb_r, sb_c, M, N, K, k_chunk, e, m->d_ws);
     else
-        hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, st, static_cast<const float*>(A), sa_r, sa_c, B, sb_r,
-                           sb_c, M, N, K, e);
+        hipLaunchKernelGGL(k_gemm<float>, grid, dim3(64), 0, st, static_cast<const float*>(A), sa_r, sa_c, B, sb_r,
+                           sb_c, M, N, K, k_chunk, e, m->d_ws);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_splitk_reduce, dim3(std::min(cdiv((int64_t)M * N, 256), 1024)), dim3(256), 0, st, m->d_ws,
+                           splits, M, N, e);
     return hipGetLastError();
 }
 
@@ -200,9 +247,9 @@ hipError_t forward(hrir_mlp* m, int n, hipStream_t st) {
     for (int l = 0; l < m->L; ++l) {
         const int k = m->sizes[l], o = m->sizes[l + 1];
         const bool last = l + 1 == m->L;
-        Epi e{m->d_p + m->b_off[l], nullptr, 0, 1, last ? 0 : 1,
+        Epi e{m->d_p + m->b_off[l], nullptr, 0, last ? 0 : 1, last ? 0 : 1,
               last ? static_cast<void*>(m->d_out) : static_cast<void*>(m->d_act[l + 1]), o};
-        hipError_t r = gemm(st, true, m->d_act[l], k, 1, m->d_p + m->w_off[l], o, 1, n, o, k, e);
+        hipError_t r = gemm(m, st, true, m->d_act[l], k, 1, m->d_p + m->w_off[l], o, 1, n, o, k, e);
         if (r != hipSuccess) return r;
     }
     return hipSuccess;
@@ -221,14 +268,14 @@ hipError_t backward(hrir_mlp* m, int n, const float* d_t, hipStream_t st) {
         const float* dz = m->d_dz[cur];
         // dW = act_l^T dz (k x o, contraction over the n rows)
         Epi ew{nullptr, nullptr, 0, 0, 0, m->d_g + m->w_off[l], o};
-        r = gemm(st, true, m->d_act[l], 1, k, dz, o, 1, k, o, n, ew);
+        r = gemm(m, st, true, m->d_act[l], 1, k, dz, o, 1, k, o, n, ew);
         if (r != hipSuccess) break;
         hipLaunchKernelGGL(k_colsum, dim3(cdiv(o, 256)), dim3(256), 0, st, dz, n, o, m->d_g + m->b_off[l]);
         r = hipGetLastError();
         if (r != hipSuccess || l == 0) break;
         // dz_{l-1} = (dz W^T) [act_l > 0]  (n x k, contraction over o)
         Epi eh{nullptr, m->d_act[l], k, 0, 0, m->d_dz[cur ^ 1], k};
-        r = gemm(st, false, dz, o, 1, m->d_p + m->w_off[l], 1, o, n, k, o, eh);
+        r = gemm(m, st, false, dz, o, 1, m->d_p + m->w_off[l], 1, o, n, k, o, eh);
         cur ^= 1;
     }
     return r;
@@ -278,6 +325,9 @@ extern "C" int mlp_create(const int32_t* sizes, int32_t n_layers, int32_t max_ba
         widest = std::max(widest, sizes[l + 1]);
     }
     m->n_params = off;
+    int64_t widest_layer = 0;
+    for (int l = 0; l < n_layers; ++l) widest_layer = std::max<int64_t>(widest_layer, (int64_t)sizes[l] * sizes[l + 1]);
+    m->ws_elems = kMaxSplits * widest_layer;
     m->n_part = std::max(1, std::min(cdiv((int64_t)max_batch * sizes[n_layers], kLossThreads), 512));
     hipError_t e = hipSuccess;
     for (float** p : {&m->d_p, &m->d_g, &m->d_m, &m->d_v})
@@ -287,6 +337,7 @@ extern "C" int mlp_create(const int32_t* sizes, int32_t n_layers, int32_t max_ba
         e = hipMalloc(&m->d_act[l], sizeof(uint16_t) * (size_t)max_batch * sizes[l]);
     if (e == hipSuccess) e = hipMalloc(&m->d_out, sizeof(float) * (size_t)max_batch * sizes[n_layers]);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&m->d_dz[i], sizeof(float) * (size_t)max_batch * widest);
+    if (e == hipSuccess) e = hipMalloc(&m->d_ws, sizeof(float) * m->ws_elems);
     if (e == hipSuccess) e = hipMalloc(&m->d_step, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&m->d_part, sizeof(double) * m->n_part);
     if (e == hipSuccess) e = hipMemset(m->d_step, 0, sizeof(int));

@@ -349,3 +349,43 @@ extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const doub
         if (status[i]) return fail(status[i], "hrir_tune_sigma: NNLS failed on row %d", i);
     return HRIR_OK;
 }
+
+// Fallback rule of the surrogate: directions are compared by the angle between
+// their unit vectors in the interaural-polar convention of the direction grid
+// (lateral angle az, polar angle el): (sin az, cos az cos el, cos az sin el).
+extern "C" int surrogate_select(const double* q_az, const double* q_el, int32_t n_q, const double* val_az,
+                                const double* val_el, const double* val_err_db, int32_t n_val, const double* meas_az,
+                                const double* meas_el, int32_t n_meas, double max_err_db, int32_t* choice) {
+    hrir::clear_error();
+    if (n_q < 0 || n_val < 1 || n_meas < 1) return fail(HRIR_EINVAL, "surrogate_select: need n_val, n_meas >= 1");
+    if ((n_q > 0 && (!q_az || !q_el || !choice)) || !val_az || !val_el || !val_err_db || !meas_az || !meas_el)
+        return fail(HRIR_EINVAL, "surrogate_select: null pointer");
+    auto unit = [](double az, double el, double* v) {
+        v[0] = std::sin(az);
+        v[1] = std::cos(az) * std::cos(el);
+        v[2] = std::cos(az) * std::sin(el);
+    };
+    std::vector<double> V((size_t)n_val * 3), Ms((size_t)n_meas * 3);
+    for (int i = 0; i < n_val; ++i) unit(val_az[i], val_el[i], &V[(size_t)i * 3]);
+    for (int i = 0; i < n_meas; ++i) unit(meas_az[i], meas_el[i], &Ms[(size_t)i * 3]);
+    // nearest by largest dot product; ties keep the lower index
+    auto nearest = [](const std::vector<double>& T, int n, const double* v) {
+        int best = 0;
+        double bd = -2.0;
+        for (int i = 0; i < n; ++i) {
+            const double d = T[(size_t)i * 3] * v[0] + T[(size_t)i * 3 + 1] * v[1] + T[(size_t)i * 3 + 2] * v[2];
+            if (d > bd) {
+                bd = d;
+                best = i;
+            }
+        }
+        return best;
+    };
+    hrir::parallel_for(n_q, [&](int64_t i) {
+        double v[3];
+        unit(q_az[i], q_el[i], v);
+        const int nv = nearest(V, n_val, v);
+        choice[i] = val_err_db[nv] > max_err_db ? nearest(Ms, n_meas, v) : -1;
+    });
+    return HRIR_OK;
+}

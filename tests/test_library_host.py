@@ -154,3 +154,25 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(ct), name
         for field, _ in ct._fields_:
             assert got[(name, field)] == getattr(ct, field).offset, (name, field)
+
+
+def test_surrogate_select_brute_force():
+    """The fallback rule against a brute-force evaluation of its definition."""
+    rng = np.random.default_rng(9)
+    q_az, q_el = rng.uniform(-1.4, 1.4, 500), rng.uniform(-0.8, 4.0, 500)
+    v_az, v_el = rng.uniform(-1.4, 1.4, 60), rng.uniform(-0.8, 4.0, 60)
+    m_az, m_el = rng.uniform(-1.4, 1.4, 90), rng.uniform(-0.8, 4.0, 90)
+    err = rng.uniform(-45, -15, 60)
+    ch = H.surrogate_select(q_az, q_el, v_az, v_el, err, m_az, m_el, -30.0)
+
+    def unit(a, e):
+        return np.stack([np.sin(a), np.cos(a) * np.cos(e), np.cos(a) * np.sin(e)], axis=-1)
+
+    Q, V, Mm = unit(q_az, q_el), unit(v_az, v_el), unit(m_az, m_el)
+    for i in range(500):
+        nv = int(np.argmax(V @ Q[i]))
+        want = int(np.argmax(Mm @ Q[i])) if err[nv] > -30.0 else -1
+        assert ch[i] == want
+    assert 0 < np.sum(ch >= 0) < 500
+    with pytest.raises(H.HrirError):
+        H.surrogate_select(q_az, q_el, [], [], [], m_az, m_el)

@@ -58,7 +58,7 @@ def test_first_adam_step_closed_form():
         np.testing.assert_allclose(q, p - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
 
 
-def test_forward_rounds_hidden_activations_only():
+def test_forward_rounds_hidden_activations_only_and_output_is_linear():
     rng = np.random.default_rng(4)
     params = synth.mlp_params(5, [4, 16, 3])
     X = rng.standard_normal((5, 4))
@@ -66,4 +66,4 @@ def test_forward_rounds_hidden_activations_only():
     h1 = cache[1][0]
     np.testing.assert_array_equal(h1, M.bf16(h1))             # hidden activations are bf16 values
     np.testing.assert_array_equal(cache[0][0], M.bf16(X))      # and so is the input
-    np.testing.assert_array_equal(y, np.maximum(h1 @ params[1][0] + params[1][1], 0.0))
+    np.testing.assert_array_equal(y, h1 @ params[1][0] + params[1][1])   # linear output layer
