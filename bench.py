@@ -452,6 +452,64 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
     return res
 
 
+def bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens, jobs, out_off, out):
+    """Per-region resonance filters (the paper's remedy for contralateral
+    error): a 1,250-direction set with head shadow on the contralateral ear
+    (its resonance low-passed, more so at lateral directions), factorized with
+    one f, and with one f per region -- ipsilateral, and the contralateral
+    side split in two by lateral angle -- each region's Alg. 1 warm-started
+    from the one-f solution (at lambda = 0 its cost then only decreases).
+    Rendered on the throughput workload's sources and rows."""
+    import synth
+    hs = synth.hrir_set(0, 25, 50, shadow=0.8)
+    X = hs.h
+
+    def agg(err, sel):
+        en = np.sum(X[sel] ** 2, axis=1)
+        return float(10 * np.log10(np.sum(10 ** (err[sel] / 10) * en) / np.sum(en)))
+
+    t0 = time.perf_counter()
+    f1 = H.factorize(X, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False)
+    lat = np.abs(np.repeat(np.sin(hs.az), 2))
+    mid = float(np.median(lat[hs.contra]))
+    reg = np.where(hs.contra, np.where(lat > mid, 2, 1), 0).astype(np.int32)
+    R = 3
+    rr = np.zeros((R, lf), np.float32)
+    p = np.zeros_like(f1["p"])
+    g = np.zeros_like(f1["g"])
+    err = np.zeros(X.shape[0])
+    for q in range(R):
+        sel = reg == q
+        fq = H.factorize(X[sel], lf, 1000, args.k, g0=np.maximum(f1["G"][sel], 1e-12), lambda0=0.0, want_cost=False)
+        rr[q] = fq["f"]
+        p[sel], g[sel], err[sel] = fq["p"], fq["g"], fq["err_db"]
+    fact_s = time.perf_counter() - t0
+    allf = np.ones(X.shape[0], bool)
+    quality = {"one_f": {"E_dB": agg(f1["err_db"], allf), "ipsi": agg(f1["err_db"], ~hs.contra),
+                         "contra": agg(f1["err_db"], hs.contra)},
+               "three_regions": {"E_dB": agg(err, allf), "ipsi": agg(err, ~hs.contra), "contra": agg(err, hs.contra)}}
+    log(f"regions: one f {quality['one_f']['E_dB']:.2f} dB (contra {quality['one_f']['contra']:.2f}), "
+        f"3 regions {quality['three_regions']['E_dB']:.2f} dB (contra {quality['three_regions']['contra']:.2f}), "
+        f"factorized in {fact_s:.1f} s")
+    plan1 = H.Plan(f1["f"].astype(np.float32), f1["p"], f1["g"], lg)
+    planR = H.Plan(rr, p, g, lg, regions=reg)
+    res = {"workload": "1,250-direction set with contralateral head shadow (shadow 0.8); 3 regions: ipsilateral, "
+                       "contralateral below / above the median lateral angle; throughput workload rows",
+           "quality": quality, "factorize_s": fact_s}
+    n_out = len(jobs) * plan1.out_len(ns)
+    alg = 4.0 * n_out + 4.0 * n_src * ns
+    for name, plan in (("one_f", plan1), ("three_regions", planR)):
+        b = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)])
+        ms, _ = time_launches(lambda: b.render(src, out), args.steps, args.warmup)
+        res[name + "_render"] = {"ms_per_step": ms, "value": n_out / (ms * 1e-3),
+                                 "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "tiles": b.info()["tiles"]}
+        log(f"regions render {name}: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s")
+        b.close()
+    plan1.close()
+    planR.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -476,6 +534,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds per streaming-loop load level (0: skip)")
     ap.add_argument("--no-sparsifier", action="store_true", help="skip the L1-NNLS sparsifier quality section")
+    ap.add_argument("--no-regions", action="store_true", help="skip the per-region resonance section")
     ap.add_argument("--surrogate-steps", type=int, default=12000,
                     help="Adam steps of the surrogate network (multiple of 1000; 0: skip the section)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -565,6 +624,8 @@ def main():
         ub.close()
         torch.cuda.empty_cache()
 
+    regions = None if args.no_regions else bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens,
+                                                         jobs, out_off, out)
     k_sweep = {}
     for kk in [int(x) for x in args.k_sweep.split(",") if x]:
         t1 = time.perf_counter()
@@ -627,6 +688,7 @@ def main():
                     "fact_iters": args.fact_iters, "sparsifiers": sparsifier},
         "legs": legs,
         "k_sweep": k_sweep,
+        "regions": regions,
         "uneven": uneven,
         "block_latency": latency,
         "serving": serving,

@@ -143,14 +143,27 @@ int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int3
  *              >= 0 (padding taps may repeat a position with gain 0).
  * k            1 <= k <= 64.  lg: reflection length, 1 <= lg <= 2048.
  * The plan copies everything to plan-owned device memory (current device)
- * and is immutable afterwards: renders on different streams may share it.
- * Errors: EINVAL (ranges, p outside [0, lg), negative or non-finite g),
- * ENOMEM, EDEVICE.
+ * and is immutable afterwards (except rows rewritten by spconv_plan_topk):
+ * renders on different streams may share it.
+ *
+ * spconv_plan_multi: one resonance filter per region of space (the paper's
+ * proposed remedy for contralateral error, Sec. IV-D: separate
+ * decompositions for sub-regions).  r is host f32[n_res][lf], 1 <= n_res <=
+ * 64; res host int32[n_filters] gives each filter's region (may be null
+ * when n_res = 1).  A source rendered at filters of several regions forms
+ * one z = r_region * s per region; batches group a source's jobs by region.
+ * Such plans render with the default kernel only (the other kernels, block
+ * rendering, streaming and moving sources refuse them with EINVAL).
+ * spconv_plan is spconv_plan_multi with n_res = 1.
+ * Errors: EINVAL (ranges, p outside [0, lg), negative or non-finite g,
+ * regions out of range), ENOMEM, EDEVICE.
  * ---------------------------------------------------------------------- */
 typedef struct hrir_plan hrir_plan;
 
 int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
                 int32_t k, int32_t lg, hrir_plan** out);
+int spconv_plan_multi(const float* r, int32_t n_res, int32_t lf, const int32_t* res, const int32_t* p,
+                      const float* g, int32_t n_filters, int32_t k, int32_t lg, hrir_plan** out);
 void spconv_plan_destroy(hrir_plan* plan);
 /* host int32[3]: lf, k, lg of the plan. */
 int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3);

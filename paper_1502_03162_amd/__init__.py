@@ -102,6 +102,8 @@ def _load() -> ctypes.CDLL:
                                    c_uint32, P_d, P_d, P_i32, P_f, P_i32, P_d, P_d]),
         "spconv_plan": (c_int, [P_f, c_int32, P_i32, P_f, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
         "spconv_plan_destroy": (None, [c_void_p]),
+        "spconv_plan_multi": (c_int, [P_f, c_int32, c_int32, P_i32, P_i32, P_f, c_int32, c_int32, c_int32,
+                                      POINTER(c_void_p)]),
         "spconv_batch_create": (c_int, [c_void_p, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32, c_int32,
                                         c_int32, c_int32, POINTER(c_void_p)]),
         "spconv_batch_render": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
@@ -162,7 +164,7 @@ def _load() -> ctypes.CDLL:
 
 
 _lib = _load()
-EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_destroy", "spconv_batch_create",
+EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_multi", "spconv_plan_destroy", "spconv_batch_create",
             "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "dense_plan",
             "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
@@ -281,19 +283,26 @@ def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4):
 # Rendering
 # ---------------------------------------------------------------------------
 class Plan:
-    """Resonance filter r and tap table (p, g) resident on the device."""
+    """Resonance filter(s) r and tap table (p, g) resident on the device.
+    r is [lf], or [n_res][lf] with `regions` giving each filter's region
+    (spconv_plan_multi)."""
 
-    def __init__(self, r, p, g, lg: int):
+    def __init__(self, r, p, g, lg: int, regions=None):
         r = np.ascontiguousarray(r, dtype=np.float32)
         p = np.ascontiguousarray(p, dtype=np.int32)
         g = np.ascontiguousarray(g, dtype=np.float32)
         if p.ndim != 2 or p.shape != g.shape:
             raise ValueError("p and g must be [n_filters][k] arrays of the same shape")
-        self.lf, self.lg = int(r.size), int(lg)
+        r2 = r.reshape(1, -1) if r.ndim == 1 else r
+        self.n_res = int(r2.shape[0])
+        self.lf, self.lg = int(r2.shape[1]), int(lg)
         self.n_filters, self.k = p.shape
+        rg = None if regions is None else np.ascontiguousarray(regions, dtype=np.int32)
+        if rg is not None and rg.shape != (self.n_filters,):
+            raise ValueError("regions must hold one region per filter")
         h = c_void_p()
-        _check(_lib.spconv_plan(_ptr(r, c_float), r.size, _ptr(p, c_int32), _ptr(g, c_float), p.shape[0],
-                                p.shape[1], lg, byref(h)))
+        _check(_lib.spconv_plan_multi(_ptr(r2, c_float), self.n_res, self.lf, None if rg is None else _ptr(rg, c_int32),
+                                      _ptr(p, c_int32), _ptr(g, c_float), p.shape[0], p.shape[1], lg, byref(h)))
         self._h = h
 
     @property

@@ -189,6 +189,9 @@ extern "C" int block_streams_create(const hrir_plan* plan, int32_t max_streams, 
     const float* dg;
     int rc = spconv_plan_shape(plan, shp);
     if (rc) return rc;
+    if (plan_view(plan).n_res > 1)
+        return fail(HRIR_EINVAL, "block_streams_create: the plan has %d resonance filters; block rendering uses one",
+                    plan_view(plan).n_res);
     rc = spconv_plan_device(plan, &dr, &dp, &dg, lk);
     if (rc) return rc;
     auto* s = new (std::nothrow) hrir_streams;

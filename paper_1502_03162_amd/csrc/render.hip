@@ -200,7 +200,9 @@ using namespace hrir;
 
 struct hrir_plan {
     int lf, lfp, k, kp, lg, n_filters, device;
-    float* d_r = nullptr;   // [lfp], zero padded
+    int n_res = 1;            // resonance filters (regions)
+    std::vector<int> res;     // region of each filter (empty when n_res == 1)
+    float* d_r = nullptr;   // [n_res][lfp], zero padded
     int* d_p = nullptr;     // [n_filters][kp], padded with (0, 0)
     float* d_g = nullptr;
 };
@@ -317,17 +319,22 @@ int launch(hrir_batch* b, const float* d_src, float* d_out, hipStream_t st) {
 
 }  // namespace
 
-extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
-                           int32_t k, int32_t lg, hrir_plan** out) {
+extern "C" int spconv_plan_multi(const float* r, int32_t n_res, int32_t lf, const int32_t* res, const int32_t* p,
+                                 const float* g, int32_t n_filters, int32_t k, int32_t lg, hrir_plan** out) {
     clear_error();
-    if (!r || !p || !g || !out) return fail(HRIR_EINVAL, "spconv_plan: null pointer");
+    if (!r || !p || !g || !out || (n_res > 1 && !res)) return fail(HRIR_EINVAL, "spconv_plan: null pointer");
     *out = nullptr;
+    if (n_res < 1 || n_res > 64) return fail(HRIR_EINVAL, "spconv_plan: n_res=%d outside [1, 64]", n_res);
     if (lf < 1 || lf > 64) return fail(HRIR_EINVAL, "spconv_plan: lf=%d outside [1, 64]", lf);
     if (k < 1 || k > 64) return fail(HRIR_EINVAL, "spconv_plan: k=%d outside [1, 64]", k);
     if (lg < 1 || lg > 2048) return fail(HRIR_EINVAL, "spconv_plan: lg=%d outside [1, 2048]", lg);
     if (n_filters < 1) return fail(HRIR_EINVAL, "spconv_plan: n_filters=%d < 1", n_filters);
-    for (int i = 0; i < lf; ++i)
+    for (int i = 0; i < n_res * lf; ++i)
         if (!std::isfinite(r[i])) return fail(HRIR_EINVAL, "spconv_plan: r[%d] not finite", i);
+    if (n_res > 1)
+        for (int f = 0; f < n_filters; ++f)
+            if (res[f] < 0 || res[f] >= n_res)
+                return fail(HRIR_EINVAL, "spconv_plan: region %d of filter %d outside [0, %d)", res[f], f, n_res);
     for (int64_t i = 0; i < (int64_t)n_filters * k; ++i) {
         if (p[i] < 0 || p[i] >= lg)
             return fail(HRIR_EINVAL, "spconv_plan: p[%lld]=%d outside [0, %d)", (long long)i, p[i], lg);
@@ -337,8 +344,10 @@ extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const f
     auto* pl = new (std::nothrow) hrir_plan;
     if (!pl) return fail(HRIR_ENOMEM, "spconv_plan: out of host memory");
     pl->lf = lf; pl->lfp = pad_lf(lf); pl->k = k; pl->kp = pad_k(k); pl->lg = lg; pl->n_filters = n_filters;
-    std::vector<float> hr(pl->lfp, 0.0f);
-    std::memcpy(hr.data(), r, sizeof(float) * lf);
+    pl->n_res = n_res;
+    if (n_res > 1) pl->res.assign(res, res + n_filters);
+    std::vector<float> hr((size_t)n_res * pl->lfp, 0.0f);
+    for (int q = 0; q < n_res; ++q) std::memcpy(hr.data() + (size_t)q * pl->lfp, r + (size_t)q * lf, sizeof(float) * lf);
     std::vector<int> hp((size_t)n_filters * pl->kp, 0);
     std::vector<float> hg((size_t)n_filters * pl->kp, 0.0f);
     for (int f = 0; f < n_filters; ++f)
@@ -360,9 +369,15 @@ extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const f
     return HRIR_OK;
 }
 
+extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const float* g, int32_t n_filters,
+                           int32_t k, int32_t lg, hrir_plan** out) {
+    return spconv_plan_multi(r, 1, lf, nullptr, p, g, n_filters, k, lg, out);
+}
+
 namespace hrir {
 PlanView plan_view(const hrir_plan* pl) {
-    return PlanView{pl->lf, pl->lfp, pl->k, pl->kp, pl->lg, pl->n_filters, pl->device, pl->d_r, pl->d_p, pl->d_g};
+    return PlanView{pl->lf, pl->lfp, pl->k, pl->kp, pl->lg, pl->n_filters, pl->device, pl->n_res,
+                    pl->d_r, pl->d_p, pl->d_g};
 }
 }  // namespace hrir
 
@@ -449,6 +464,9 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, %d]", tile,
                     tile_unit, tile_unit, tile_max);
     if (group < 0) return fail(HRIR_EINVAL, "spconv_batch_create: group < 0");
+    if (plan->n_res > 1 && kind != KIND_QUAD)
+        return fail(HRIR_EINVAL, "spconv_batch_create: a plan with %d resonance filters needs the default kernel",
+                    plan->n_res);
     const int lf = plan->lf, lg = plan->lg;
     for (int i = 0; i < n_src; ++i) {
         if (src_len[i] < 1 || src_len[i] > (int64_t)INT32_MAX - lf - lg)
@@ -470,10 +488,15 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         b->src_extent = std::max(b->src_extent, src_off[s] + src_len[s]);
         b->out_extent = std::max(b->out_extent, jobs[j].out_off + src_len[s] + lf + lg - 2);
     }
-    // Jobs grouped by source (stable, so a source's jobs keep their order).
+    // Jobs grouped by source, then by region (stable, so a group's jobs keep
+    // their order): a tile's jobs share one z = r_region * s.
+    auto region = [plan](int filt) { return plan->n_res > 1 ? plan->res[filt] : 0; };
     std::vector<int> order(n_jobs);
     for (int j = 0; j < n_jobs; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [jobs](int a, int c) { return jobs[a].src < jobs[c].src; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        if (jobs[a].src != jobs[c].src) return jobs[a].src < jobs[c].src;
+        return region(jobs[a].filt) < region(jobs[c].filt);
+    });
     std::vector<JobDesc> hj(n_jobs);
     for (int j = 0; j < n_jobs; ++j) hj[j] = JobDesc{jobs[order[j]].out_off, jobs[order[j]].filt, 0};
     std::vector<TileDesc> ht;
@@ -483,8 +506,9 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     int max_group = 0;
     for (int j0 = 0; j0 < n_jobs;) {
         const int s = jobs[order[j0]].src;
+        const int rg = region(jobs[order[j0]].filt);
         int j1 = j0;
-        while (j1 < n_jobs && jobs[order[j1]].src == s) ++j1;
+        while (j1 < n_jobs && jobs[order[j1]].src == s && region(jobs[order[j1]].filt) == rg) ++j1;
         const int njs = j1 - j0;
         const int gsz = group > 0 ? std::min(group, njs) : njs;
         max_group = std::max(max_group, gsz);
@@ -492,7 +516,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         for (int g0 = j0; g0 < j1; g0 += gsz)
             for (int64_t t0 = 0; t0 < out_len; t0 += tile)
                 ht.push_back(TileDesc{src_off[s], (int32_t)src_len[s], (int32_t)out_len, (int32_t)t0, g0,
-                                      std::min(gsz, j1 - g0), 0});
+                                      std::min(gsz, j1 - g0), rg});
         if (flags & SPCONV_UNFUSED) {
             const int64_t nz = src_len[s] + lf - 1;
             for (int64_t v0 = 0; v0 < nz; v0 += kZChunk)

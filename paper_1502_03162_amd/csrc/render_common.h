@@ -26,7 +26,7 @@ struct TileDesc {               // 32 bytes
     int32_t t0;                 // first output sample of the tile
     int32_t job_begin;          // into the job table (jobs sorted by source)
     int32_t job_count;
-    int32_t pad;
+    int32_t res;                // resonance filter (region) of the tile's jobs
 };
 
 struct JobDesc {                // 16 bytes
@@ -170,7 +170,7 @@ constexpr int kQuadTileMax = 4096;
 
 // Shape and device tables of a plan (render.hip owns the struct).
 struct PlanView {
-    int lf, lfp, k, kp, lg, n_filters, device;
+    int lf, lfp, k, kp, lg, n_filters, device, n_res;
     float* d_r;
     int* d_p;
     float* d_g;

@@ -239,6 +239,7 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     if (!plan || !out) return fail(HRIR_EINVAL, "moving_create: null pointer");
     *out = nullptr;
     const PlanView pv = plan_view(plan);
+    if (pv.n_res > 1) return fail(HRIR_EINVAL, "moving_create: the plan has %d resonance filters; moving sources use one", pv.n_res);
     if (n_src < 1) return fail(HRIR_EINVAL, "moving_create: n_src=%d < 1", n_src);
     if (src_len < 1 || src_len > (int64_t)1 << 30) return fail(HRIR_EINVAL, "moving_create: src_len out of range");
     if (seg_len < kMovItem || seg_len % kMovItem)

@@ -37,7 +37,7 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
                                                  const JobDesc* __restrict__ jobs, const float* __restrict__ r,
                                                  const int* __restrict__ P, const float* __restrict__ Gv,
                                                  float* __restrict__ out, int lg, int TB, float* lds) {
-    quad_stage<LFP>(td, src, r, lg, TB, lds);
+    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds);
     const int tid = threadIdx.x;
     const int H = lg - 1;
     const int CS = quad_cs(TB, H);

@@ -65,6 +65,7 @@ class HrirSet:
     az: np.ndarray       # f64[D] radians
     el: np.ndarray       # f64[D] radians
     onset: np.ndarray    # i64[F]
+    contra: np.ndarray = None   # bool[F]: the ear on the far side of the head from the source
 
     @property
     def n_filters(self) -> int:
@@ -72,7 +73,7 @@ class HrirSet:
 
 
 def hrir_set(seed: int, n_az: int, n_el: int, lf: int = 32, m: int = M_TAPS,
-             n_pinna: int = 11, noise: float = 1e-3) -> HrirSet:
+             n_pinna: int = 11, noise: float = 1e-3, shadow: float = 0.0) -> HrirSet:
     """Synthetic HRIR set: F = 2 * n_az * n_el filters of m taps.
 
     Reflection filter (length lg = m - lf + 1): a unit tap at the onset
@@ -81,6 +82,11 @@ def hrir_set(seed: int, n_az: int, n_el: int, lf: int = 32, m: int = M_TAPS,
     offsets move smoothly with elevation and whose gains decay geometrically
     (u_j * 0.8**j, u_j ~ U(0.1, 1)), plus non-negative noise U(0, noise) on
     every tap.  HRIR = resonance * reflection (full convolution, length m).
+
+    shadow > 0 adds head shadow on the contralateral ear (the later onset):
+    its HRIR is (resonance * lp) * reflection, truncated to m taps, with the
+    low-pass lp_j = a^j / sum (j < 8), a = shadow |itd| / itd(90 deg), so the
+    resonance of that ear differs with direction and from the ipsilateral one.
     """
     rng = np.random.default_rng(seed)
     lg = m - lf + 1
@@ -92,6 +98,8 @@ def hrir_set(seed: int, n_az: int, n_el: int, lf: int = 32, m: int = M_TAPS,
     w90 = woodworth_itd(np.array(math.pi / 2.0))
     g = np.zeros((2 * D, lg))
     onset = np.zeros(2 * D, dtype=np.int64)
+    contra = np.zeros(2 * D, dtype=bool)
+    res_f = [r] * (2 * D)
     for d in range(D):
         itd = woodworth_itd(np.array(az[d])) / w90
         for e in range(2):
@@ -99,6 +107,11 @@ def hrir_set(seed: int, n_az: int, n_el: int, lf: int = 32, m: int = M_TAPS,
             sign = -1.0 if e == 0 else 1.0
             on = int(round(20.0 + sign * 20.0 * float(itd)))
             on = min(max(on, 0), 40)
+            contra[f] = sign * float(itd) > 0.0
+            if shadow > 0.0 and contra[f]:
+                a = shadow * abs(float(itd))
+                lp = a ** np.arange(8)
+                res_f[f] = np.convolve(r, lp / lp.sum())
             onset[f] = on
             g[f, on] += 1.0
             u = rng.uniform(0.1, 1.0, size=n_pinna)
@@ -106,8 +119,8 @@ def hrir_set(seed: int, n_az: int, n_el: int, lf: int = 32, m: int = M_TAPS,
             for j in range(n_pinna):
                 g[f, on + off[j]] += u[j] * 0.8 ** (j + 1)
             g[f] += rng.uniform(0.0, noise, size=lg)
-    h = np.stack([np.convolve(r, g[f])[:m] for f in range(2 * D)])
-    return HrirSet(r=r, g=g, h=h, az=az, el=el, onset=onset)
+    h = np.stack([np.convolve(res_f[f], g[f])[:m] for f in range(2 * D)])
+    return HrirSet(r=r, g=g, h=h, az=az, el=el, onset=onset, contra=contra)
 
 
 # ---------------------------------------------------------------------------

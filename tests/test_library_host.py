@@ -176,3 +176,15 @@ def test_surrogate_select_brute_force():
     assert 0 < np.sum(ch >= 0) < 500
     with pytest.raises(H.HrirError):
         H.surrogate_select(q_az, q_el, [], [], [], m_az, m_el)
+
+
+def test_region_labels_are_validated_before_any_device_call():
+    r = np.ones((2, 4), dtype=np.float32)
+    p = np.zeros((3, 2), dtype=np.int32)
+    g = np.ones((3, 2), dtype=np.float32)
+    for regions in ([0, 2, 1], [0, -1, 1]):
+        with pytest.raises(H.HrirError) as e:
+            H.Plan(r, p, g, 9, regions=regions)
+        assert e.value.code == H.HRIR_EINVAL and "region" in str(e.value)
+    with pytest.raises(H.HrirError):
+        H.Plan(r, p, g, 9)                                  # two resonance filters need labels
