@@ -455,7 +455,9 @@ void stream_close(hrir_server* server);
  *                   n_seg - 1); in its first `fade` (0..256) samples, u =
  *                   t - j seg_len < fade with j >= 1, the output is
  *                   a y_j + (1 - a) y_{j-1}, a = (u + 1) / fade, y_j the render
- *                   with segment j's filter.  The plan must outlive the object.
+ *                   with segment j's filter.  tile: outputs per workgroup, a
+ *                   multiple of 256 up to 4096 (0: 2048).  The plan must
+ *                   outlive the object.
  * moving_render     seg_filt host i32[n_src][n_seg][2] plan rows (left,
  *                   right) per segment, validated and staged through pinned
  *                   memory (double buffered).  d_out device f32: the row of
@@ -470,7 +472,7 @@ int spconv_plan_topk(hrir_plan* plan, int32_t first_row, const float* d_dense, i
                      int32_t width, void* stream);
 int spconv_plan_read(const hrir_plan* plan, int32_t first_row, int32_t n_rows, int32_t* p_out, float* g_out);
 int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_len, int32_t seg_len, int32_t fade,
-                  hrir_moving** out);
+                  int32_t tile, hrir_moving** out);
 int moving_render(hrir_moving* moving, const float* d_src, int64_t src_elems, const int32_t* seg_filt, float* d_out,
                   int64_t out_stride, int64_t out_elems, void* stream);
 int moving_info(const hrir_moving* moving, int64_t* info4);
@@ -542,7 +544,9 @@ void mlp_destroy(hrir_mlp* mlp);
  * pair 2d, 2d + 1 with d < n_filters / 2) that changes every ~16 blocks.
  * A refused block (EAGAIN) is retried until admitted; its latency counts
  * from its arrival time.  rate_hz <= 0 submits back to back for duration_s
- * (the saturation rate).  At most max_blocks blocks are submitted.  A
+ * (the saturation rate).  At most max_blocks blocks are submitted.  With
+ * submit_threads = T > 1 the arrivals come from T threads, each a Poisson
+ * process of rate_hz / T over its own streams.  A
  * polling thread collects the results; the call returns when all are in,
  * or with EDEVICE if none arrives for 30 s after submission ends.
  * Latencies: arrival -> done (p50/p99/max) and submit -> done (p50/p99).
@@ -559,6 +563,8 @@ typedef struct {
     int64_t max_blocks;
     const float* signal;     /* host f32[signal_len] */
     int64_t signal_len;
+    int32_t submit_threads;  /* submitting threads (0 or 1: one); thread t serves streams s % T == t */
+    int32_t pad;
 } stream_load;
 
 typedef struct {

@@ -69,7 +69,7 @@ assert ctypes.sizeof(HrirResult) == 56
 class StreamLoad(ctypes.Structure):
     _fields_ = [("n_streams", c_int32), ("block_min", c_int32), ("block_max", c_int32), ("n_filters", c_int32),
                 ("rate_hz", c_double), ("duration_s", c_double), ("seed", c_uint64), ("max_blocks", c_int64),
-                ("signal", POINTER(c_float)), ("signal_len", c_int64)]
+                ("signal", POINTER(c_float)), ("signal_len", c_int64), ("submit_threads", c_int32), ("pad", c_int32)]
 
 
 class StreamLoadStats(ctypes.Structure):
@@ -142,7 +142,7 @@ def _load() -> ctypes.CDLL:
         "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_double, P_d, P_d]),
         "spconv_plan_topk": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p]),
         "spconv_plan_read": (c_int, [c_void_p, c_int32, c_int32, P_i32, P_f]),
-        "moving_create": (c_int, [c_void_p, c_int32, c_int64, c_int32, c_int32, POINTER(c_void_p)]),
+        "moving_create": (c_int, [c_void_p, c_int32, c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
         "moving_render": (c_int, [c_void_p, c_void_p, c_int64, P_i32, c_void_p, c_int64, c_int64, c_void_p]),
         "moving_info": (c_int, [c_void_p, P_i64]),
         "moving_destroy": (None, [c_void_p]),
@@ -627,12 +627,14 @@ class Server:
         return dict(zip(keys, (int(x) for x in v)))
 
     def loadgen(self, signal, n_streams: int, rate_hz: float, duration_s: float, block_min: int = 64,
-                block_max: int = 1024, n_filters: int = 2, seed: int = 0, max_blocks: int = 1 << 22) -> dict:
+                block_max: int = 1024, n_filters: int = 2, seed: int = 0, max_blocks: int = 1 << 22,
+                submit_threads: int = 1) -> dict:
         """Runs the library's open-loop Poisson load generator (stream_loadgen)
         against this server; rate_hz <= 0 submits back to back."""
         sig = np.ascontiguousarray(signal, dtype=np.float32)
         cfg = StreamLoad(int(n_streams), int(block_min), int(block_max), int(n_filters), float(rate_hz),
-                         float(duration_s), int(seed), int(max_blocks), _ptr(sig, c_float), sig.size)
+                         float(duration_s), int(seed), int(max_blocks), _ptr(sig, c_float), sig.size,
+                         int(submit_threads), 0)
         st = StreamLoadStats()
         _check(_lib.stream_loadgen(self._h, byref(cfg), byref(st)))
         return {name: getattr(st, name) for name, _ in StreamLoadStats._fields_}
@@ -749,10 +751,11 @@ class Moving:
     """Moving sources (moving_*): n_src equal-length sources whose direction
     changes every seg_len samples, with a linear crossfade of `fade` samples."""
 
-    def __init__(self, plan: Plan, n_src: int, src_len: int, seg_len: int, fade: int):
+    def __init__(self, plan: Plan, n_src: int, src_len: int, seg_len: int, fade: int, tile: int = 0):
         self.plan = plan
         hd = c_void_p()
-        _check(_lib.moving_create(plan.handle, int(n_src), int(src_len), int(seg_len), int(fade), byref(hd)))
+        _check(_lib.moving_create(plan.handle, int(n_src), int(src_len), int(seg_len), int(fade), int(tile),
+                                  byref(hd)))
         self._h = hd
         v = np.zeros(4, dtype=np.int64)
         _check(_lib.moving_info(hd, _ptr(v, c_int64)))

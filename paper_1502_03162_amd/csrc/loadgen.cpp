@@ -39,7 +39,8 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     hrir::clear_error();
     if (!srv || !cfg || !st || !cfg->signal) return fail(HRIR_EINVAL, "stream_loadgen: null pointer");
     if (cfg->n_streams < 1 || cfg->block_min < 1 || cfg->block_max < cfg->block_min || cfg->block_max > 4096 ||
-        cfg->signal_len < cfg->block_max || cfg->n_filters < 2 || cfg->duration_s <= 0.0 || cfg->max_blocks < 1)
+        cfg->signal_len < cfg->block_max || cfg->n_filters < 2 || cfg->duration_s <= 0.0 || cfg->max_blocks < 1 ||
+        cfg->submit_threads < 0 || cfg->submit_threads > 64)
         return fail(HRIR_EINVAL, "stream_loadgen: bad configuration");
     int64_t info[8];
     int rc = stream_info(srv, info);
@@ -82,50 +83,72 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
         }
     });
 
-    std::mt19937_64 rng(cfg->seed);
-    std::uniform_int_distribution<int> len_d(cfg->block_min, cfg->block_max);
-    std::uniform_int_distribution<int> sid_d(0, cfg->n_streams - 1);
-    std::uniform_int_distribution<int> dir_d(0, cfg->n_filters / 2 - 1);
-    std::uniform_int_distribution<int64_t> off_d(0, cfg->signal_len - cfg->block_max);
-    std::exponential_distribution<double> gap_d(cfg->rate_hz > 0.0 ? cfg->rate_hz : 1.0);
-    std::vector<int> dir((size_t)cfg->n_streams);
-    for (int& d : dir) d = dir_d(rng);
+    // T submitting threads, each a Poisson process of rate / T over the
+    // streams s with s % T == t; thread t uses the tags t, t + T, t + 2T, ...
+    const int T = std::max(1, std::min(cfg->submit_threads > 0 ? cfg->submit_threads : 1, cfg->n_streams));
     const bool open_loop = cfg->rate_hz > 0.0;
     const int64_t t0 = now_ns();
     const int64_t t_stop = t0 + (int64_t)(cfg->duration_s * 1e9);
-    double t_next = (double)t0;
-    int64_t n = 0;
-    while (n < cap && poll_error == 0) {
-        int64_t t_arr;
-        if (open_loop) {
-            t_next += gap_d(rng) * 1e9;
-            t_arr = (int64_t)t_next;
-            if (t_arr >= t_stop) break;
-            for (int64_t t; (t = now_ns()) < t_arr;)
-                if (t_arr - t > 200000) std::this_thread::sleep_for(std::chrono::microseconds(50));
-        } else {
-            t_arr = now_ns();
-            if (t_arr >= t_stop) break;
-        }
-        const int sid = sid_d(rng);
-        if ((rng() & 15) == 0) dir[(size_t)sid] = dir_d(rng);   // a direction change every ~16 blocks
-        const int len = len_d(rng);
-        const float* blk = cfg->signal + off_d(rng);
-        arrival[(size_t)n] = t_arr;
+    std::atomic<int> sub_error{0};
+    std::vector<int64_t> sent(T, 0);
+    auto submitter = [&](int t) {
+        std::mt19937_64 rng(cfg->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(t + 1));
+        const int my_streams = (cfg->n_streams - t + T - 1) / T;
+        std::uniform_int_distribution<int> len_d(cfg->block_min, cfg->block_max);
+        std::uniform_int_distribution<int> sid_d(0, my_streams - 1);
+        std::uniform_int_distribution<int> dir_d(0, cfg->n_filters / 2 - 1);
+        std::uniform_int_distribution<int64_t> off_d(0, cfg->signal_len - cfg->block_max);
+        std::exponential_distribution<double> gap_d(open_loop ? cfg->rate_hz / T : 1.0);
+        std::vector<int> dir((size_t)my_streams);
+        for (int& d : dir) d = dir_d(rng);
+        double t_next = (double)t0;
+        int64_t j = 0;
         for (;;) {
-            rc = stream_submit(srv, sid, blk, len, 2 * dir[(size_t)sid], 2 * dir[(size_t)sid] + 1, (uint64_t)n);
-            if (rc != HRIR_EAGAIN) break;
-            std::this_thread::yield();
+            const int64_t tag = j * T + t;
+            if (tag >= cap || poll_error != 0 || sub_error != 0) break;
+            int64_t t_arr;
+            if (open_loop) {
+                t_next += gap_d(rng) * 1e9;
+                t_arr = (int64_t)t_next;
+                if (t_arr >= t_stop) break;
+                for (int64_t tn; (tn = now_ns()) < t_arr;)
+                    if (t_arr - tn > 200000) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            } else {
+                t_arr = now_ns();
+                if (t_arr >= t_stop) break;
+            }
+            const int ls = sid_d(rng);
+            const int sid = ls * T + t;
+            if ((rng() & 15) == 0) dir[(size_t)ls] = dir_d(rng);    // a direction change every ~16 blocks
+            const int len = len_d(rng);
+            const float* blk = cfg->signal + off_d(rng);
+            arrival[(size_t)tag] = t_arr;
+            int r;
+            for (;;) {
+                r = stream_submit(srv, sid, blk, len, 2 * dir[(size_t)ls], 2 * dir[(size_t)ls] + 1, (uint64_t)tag);
+                if (r != HRIR_EAGAIN) break;
+                std::this_thread::yield();
+            }
+            if (r) {
+                sub_error = r;
+                break;
+            }
+            ++j;
+            submitted.fetch_add(1);
         }
-        if (rc) break;
-        ++n;
-        submitted = n;
-    }
+        sent[(size_t)t] = j;
+    };
+    std::vector<std::thread> subs;
+    for (int t = 1; t < T; ++t) subs.emplace_back(submitter, t);
+    submitter(0);
+    for (auto& th : subs) th.join();
+    const int64_t n = submitted.load();
+    rc = sub_error.load();
     const int64_t t_sub_end = now_ns();
     give_up_ns = t_sub_end + 30000000000LL;
     submit_done = true;
     poller.join();
-    if (rc) return rc;
+    if (rc) return fail(rc, "stream_loadgen: a submission failed");
     if (poll_error)
         return fail(poll_error, "stream_loadgen: %s", poll_error == HRIR_EDEVICE && n_done < submitted
                                                           ? "results stopped arriving for 30 s"

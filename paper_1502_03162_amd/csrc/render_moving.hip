@@ -234,7 +234,7 @@ int with_lf_k(int lfp, int kp, F&& f) {
 }  // namespace
 
 extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_len, int32_t seg_len, int32_t fade,
-                             hrir_moving** out) {
+                             int32_t tile, hrir_moving** out) {
     clear_error();
     if (!plan || !out) return fail(HRIR_EINVAL, "moving_create: null pointer");
     *out = nullptr;
@@ -245,6 +245,10 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     if (seg_len < kMovItem || seg_len % kMovItem)
         return fail(HRIR_EINVAL, "moving_create: seg_len=%d must be a positive multiple of %d", seg_len, kMovItem);
     if (fade < 0 || fade > kMovItem) return fail(HRIR_EINVAL, "moving_create: fade=%d outside [0, %d]", fade, kMovItem);
+    if (tile == 0) tile = 2048;
+    if (tile < kMovItem || tile % kMovItem || tile > kQuadTileMax)
+        return fail(HRIR_EINVAL, "moving_create: tile=%d must be a multiple of %d in [%d, %d]", tile, kMovItem,
+                    kMovItem, kQuadTileMax);
     auto* m = new (std::nothrow) hrir_moving;
     if (!m) return fail(HRIR_ENOMEM, "moving_create: out of host memory");
     m->plan = plan;
@@ -252,6 +256,7 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     m->src_len = src_len;
     m->seg_len = seg_len;
     m->fade = fade;
+    m->TB = tile;
     m->n_seg = (int)((src_len + seg_len - 1) / seg_len);
     m->out_len = src_len + pv.lf + pv.lg - 2;
     m->lds = sizeof(float) * (size_t)lds_quad_len(m->TB, pv.lg, pv.lfp);

@@ -51,6 +51,7 @@ struct Gen {
     int64_t seq = -1;
     GenState state = kFree;
     int n_jobs = 0, max_m = 0, remaining = 0;
+    int writers = 0;                       // submissions still copying their block in
     bool failed = false;                   // its launch failed: no results
     int64_t in_used = 0, out_used = 0;     // input floats; output samples per ear
     int64_t t_launch = 0, t_done = 0;
@@ -126,6 +127,7 @@ void open_gen(hrir_server* s, int64_t seq) {
     g.in_used = 0;
     g.out_used = 0;
     g.remaining = 0;
+    g.writers = 0;
     g.failed = false;
     g.tag.clear();
     g.t_submit.clear();
@@ -160,26 +162,44 @@ int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, i
                 uint64_t tag, bool end, const char* fn) {
     const int m = end ? s->tail : n;
     const int64_t n_in = end ? 0 : n;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
-    if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
-    const int64_t q = place(s, stream, m, n_in);
-    if (q < 0) {
-        ++s->n_eagain;
-        return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+    Gen* gp = nullptr;
+    int64_t in_off = 0;
+    {
+        // reserve the job and its input space; the block is copied after the
+        // lock is released (the loop thread launches a generation only when
+        // no copy into it is under way)
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
+        if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
+        const int64_t q = place(s, stream, m, n_in);
+        if (q < 0) {
+            ++s->n_eagain;
+            return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+        }
+        Gen& g = s->gen(q);
+        const int i = g.n_jobs++;
+        in_off = g.in_used;
+        g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, in_off,
+                           2 * g.out_used};
+        g.in_used += n_in;
+        g.out_used += m;
+        g.max_m = std::max(g.max_m, m);
+        g.tag.push_back(tag);
+        g.t_submit.push_back(now_ns());
+        s->last_seq[stream] = q;
+        if (n_in) {
+            ++g.writers;
+            gp = &g;
+        } else {
+            s->cv_work.notify_all();
+        }
     }
-    Gen& g = s->gen(q);
-    const int i = g.n_jobs++;
-    g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, g.in_used,
-                       2 * g.out_used};
-    if (n_in) std::memcpy(g.h_in + g.in_used, block, sizeof(float) * (size_t)n_in);
-    g.in_used += n_in;
-    g.out_used += m;
-    g.max_m = std::max(g.max_m, m);
-    g.tag.push_back(tag);
-    g.t_submit.push_back(now_ns());
-    s->last_seq[stream] = q;
-    s->cv_work.notify_all();
+    if (gp) {
+        std::memcpy(gp->h_in + in_off, block, sizeof(float) * (size_t)n_in);
+        std::lock_guard<std::mutex> lk(s->mu);
+        --gp->writers;
+        s->cv_work.notify_all();
+    }
     return HRIR_OK;
 }
 
@@ -213,7 +233,7 @@ void dispatcher_main(hrir_server* s) {
             if (s->err_code) return true;
             const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
             if (s->closing && !ready) return true;
-            return ready && s->next_launch - s->next_done < kDepth;
+            return ready && s->gen(s->next_launch).writers == 0 && s->next_launch - s->next_done < kDepth;
         });
         const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
         if (s->err_code || (s->closing && !ready)) {
@@ -263,7 +283,10 @@ void completer_main(hrir_server* s) {
         lk.unlock();
         hipError_t e = hipSuccess;
         if (!failed)
-            while ((e = hipEventQuery(g.ev_done)) == hipErrorNotReady) std::this_thread::yield();
+            while ((e = hipEventQuery(g.ev_done)) == hipErrorNotReady) {
+                // back off between queries: the loop thread's enqueues share the runtime
+                for (int i = 0; i < 64; ++i) __builtin_ia32_pause();
+            }
         const int64_t t_done = now_ns();
         if (e != hipSuccess) {
             set_error(s, "stream loop completion", e);

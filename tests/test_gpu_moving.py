@@ -121,3 +121,27 @@ def test_moving_argument_errors(dev):
         h.plan_topk(plan, 3, torch.zeros((2, 40), device=dev), 40)      # rows 3, 4: past the plan
     mv.close()
     plan.close()
+
+
+def test_moving_tile_lengths_agree_bitwise(dev):
+    import torch
+    h = H()
+    n, seg, fade, n_src, F = 7000, 512, 64, 2, 9
+    r, p, g, srcs, rng = _moving_case(41, n_src, n, 32, 169, 16, F)
+    plan = h.Plan(r, p, g, 169)
+    src = torch.from_numpy(srcs.reshape(-1)).to(dev)
+    outs = []
+    for tile in (0, 256, 1024, 4096):
+        mv = h.Moving(plan, n_src, n, seg, fade, tile)
+        if not outs:
+            seg_filt = rng.integers(0, F, (n_src, mv.n_seg, 2)).astype(np.int32)
+        out = torch.zeros(2 * n_src * mv.out_len, device=dev)
+        mv.render(src, seg_filt, out, mv.out_len)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        mv.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    with pytest.raises(h.HrirError):
+        h.Moving(plan, n_src, n, seg, fade, 300)
+    plan.close()
