@@ -248,7 +248,9 @@ def bench_serving(H, fac, r, lg, args):
         st["label"] = label
         runs.append(st)
         log(f"serving {label}: {st['achieved_hz']:.4g} blocks/s, {st['out_samples_per_s']:.3g} samples/s, "
-            f"p50 {st['p50_ms'] * 1e3:.0f} us, p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f}")
+            f"p50 {st['p50_ms'] * 1e3:.0f} us, p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f} "
+            f"(p99 parts: admit {st['p99_admit_ms'] * 1e3:.0f}, server {st['p99_server_ms'] * 1e3:.0f}, "
+            f"collect {st['p99_collect_ms'] * 1e3:.0f} us)")
         return st
 
     sat = run("saturation", 0, 2)

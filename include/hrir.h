@@ -549,7 +549,10 @@ void mlp_destroy(hrir_mlp* mlp);
  * process of rate_hz / T over its own streams.  A
  * polling thread collects the results; the call returns when all are in,
  * or with EDEVICE if none arrives for 30 s after submission ends.
- * Latencies: arrival -> done (p50/p99/max) and submit -> done (p50/p99).
+ * A refused block is retried after a growing pause that leaves the server's
+ * lock alone.  Latencies: arrival -> done (p50/p99/max), submit -> done
+ * (p50/p99), and the two parts outside the server: arrival -> admitted and
+ * done -> collected (p99/max).
  * The server must not be polled by anyone else meanwhile.
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -580,6 +583,8 @@ typedef struct {
     double mean_batch;       /* blocks per launch */
     double p50_ms, p99_ms, max_ms;
     double p50_server_ms, p99_server_ms;
+    double p99_admit_ms, max_admit_ms;     /* arrival -> admitted by stream_submit */
+    double p99_collect_ms, max_collect_ms; /* done -> collected by the polling thread */
 } stream_load_stats;
 
 int stream_loadgen(hrir_server* server, const stream_load* cfg, stream_load_stats* stats);

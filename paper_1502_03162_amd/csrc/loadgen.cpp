@@ -47,9 +47,10 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     if (rc) return rc;
     const int64_t launches0 = info[0], eagain0 = info[3];
     const int64_t cap = cfg->max_blocks;
-    std::vector<int64_t> arrival((size_t)cap), lat, lat_srv;
+    std::vector<int64_t> arrival((size_t)cap), admit((size_t)cap, -1), lat, lat_srv, collect;
     lat.reserve((size_t)cap);
     lat_srv.reserve((size_t)cap);
+    collect.reserve((size_t)cap);
     std::atomic<int64_t> submitted{0};
     std::atomic<bool> submit_done{false};
     std::atomic<int64_t> give_up_ns{INT64_MAX};      // set once submission ends
@@ -64,10 +65,12 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
                 poll_error = n;
                 return;
             }
+            const int64_t t_got = now_ns();
             for (int i = 0; i < n; ++i) {
                 const hrir_result& r = res[(size_t)i];
                 lat.push_back(r.t_done_ns - arrival[(size_t)r.tag]);
                 lat_srv.push_back(r.t_done_ns - r.t_submit_ns);
+                collect.push_back(t_got - r.t_done_ns);
                 out_samples += 2 * (int64_t)r.n;
                 t_last_done = std::max(t_last_done, r.t_done_ns);
             }
@@ -124,15 +127,19 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
             const float* blk = cfg->signal + off_d(rng);
             arrival[(size_t)tag] = t_arr;
             int r;
-            for (;;) {
+            for (int tries = 0;; ++tries) {
                 r = stream_submit(srv, sid, blk, len, 2 * dir[(size_t)ls], 2 * dir[(size_t)ls] + 1, (uint64_t)tag);
                 if (r != HRIR_EAGAIN) break;
-                std::this_thread::yield();
+                // back off without touching the server's lock: retrying at
+                // full speed would hold up the threads that free the room
+                const int spins = 64 << std::min(tries, 5);
+                for (int i = 0; i < spins; ++i) __builtin_ia32_pause();
             }
             if (r) {
                 sub_error = r;
                 break;
             }
+            admit[(size_t)tag] = now_ns() - t_arr;
             ++j;
             submitted.fetch_add(1);
         }
@@ -171,5 +178,13 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     st->max_ms = pct(lat, 1.0);
     st->p50_server_ms = pct(lat_srv, 0.50);
     st->p99_server_ms = pct(lat_srv, 0.99);
+    std::vector<int64_t> adm;
+    adm.reserve((size_t)n);
+    for (int64_t a : admit)
+        if (a >= 0) adm.push_back(a);
+    st->p99_admit_ms = pct(adm, 0.99);
+    st->max_admit_ms = pct(adm, 1.0);
+    st->p99_collect_ms = pct(collect, 0.99);
+    st->max_collect_ms = pct(collect, 1.0);
     return HRIR_OK;
 }

@@ -141,6 +141,17 @@ void release_handed(hrir_server* s) {
     }
 }
 
+// Takes the server lock for a short critical section: spin on try_lock for
+// about a microsecond before blocking, so that submitting threads that
+// meet at the lock hand it over without sleeping in the kernel.
+std::unique_lock<std::mutex> lock_short(std::mutex& mu) {
+    for (int i = 0; i < 64; ++i) {
+        if (mu.try_lock()) return std::unique_lock<std::mutex>(mu, std::adopt_lock);
+        for (int j = 0; j < 16; ++j) __builtin_ia32_pause();
+    }
+    return std::unique_lock<std::mutex>(mu);
+}
+
 // Places one job (block or flush) for `stream` in the oldest generation that
 // can take it.  Lock held.  Returns the generation or -1 (no room: EAGAIN).
 int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
@@ -158,17 +169,28 @@ int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
     }
 }
 
+// Wakes the loop thread when generation q has just become launchable (it
+// is the next to launch, holds a job, no copy into it is under way and a
+// device slot is free).  Every other change that can make it launchable
+// notifies on its own (a completion frees a slot; close; an error), so a
+// submission that does not complete this condition wakes nobody: the loop
+// thread is not woken once per block.  Lock held.
+void wake_dispatcher(hrir_server* s, int64_t q) {
+    if (q == s->next_launch && s->gen(q).n_jobs > 0 && s->gen(q).writers == 0 && s->next_launch - s->next_done < kDepth)
+        s->cv_work.notify_one();
+}
+
 int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, int32_t filt_l, int32_t filt_r,
                 uint64_t tag, bool end, const char* fn) {
     const int m = end ? s->tail : n;
     const int64_t n_in = end ? 0 : n;
     Gen* gp = nullptr;
-    int64_t in_off = 0;
+    int64_t in_off = 0, gq = -1;
     {
         // reserve the job and its input space; the block is copied after the
         // lock is released (the loop thread launches a generation only when
         // no copy into it is under way)
-        std::lock_guard<std::mutex> lk(s->mu);
+        auto lk = lock_short(s->mu);
         if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
         if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
         const int64_t q = place(s, stream, m, n_in);
@@ -178,6 +200,7 @@ int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, i
         }
         Gen& g = s->gen(q);
         const int i = g.n_jobs++;
+        gq = q;
         in_off = g.in_used;
         g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, in_off,
                            2 * g.out_used};
@@ -190,15 +213,14 @@ int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, i
         if (n_in) {
             ++g.writers;
             gp = &g;
-        } else {
-            s->cv_work.notify_all();
+        } else if (i == 0) {
+            wake_dispatcher(s, q);
         }
     }
     if (gp) {
         std::memcpy(gp->h_in + in_off, block, sizeof(float) * (size_t)n_in);
-        std::lock_guard<std::mutex> lk(s->mu);
-        --gp->writers;
-        s->cv_work.notify_all();
+        auto lk = lock_short(s->mu);
+        if (--gp->writers == 0) wake_dispatcher(s, gq);
     }
     return HRIR_OK;
 }
@@ -460,10 +482,9 @@ extern "C" int stream_poll(hrir_server* s, hrir_result* out, int32_t max, int32_
     clear_error();
     if (!s || (max > 0 && !out)) return fail(HRIR_EINVAL, "stream_poll: null pointer");
     if (max < 0) return fail(HRIR_EINVAL, "stream_poll: max=%d < 0", max);
-    std::unique_lock<std::mutex> lk(s->mu);
+    auto lk = lock_short(s->mu);
     // results handed out by the previous poll are no longer referenced
     release_handed(s);
-    s->cv_work.notify_all();
     // wake on results or an error; never wait when nothing is queued or running
     auto pending = [&] { return !s->results.empty() || s->err_code || s->next_done == s->tail_seq; };
     if (timeout_us < 0)
