@@ -140,13 +140,34 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_grad(const float* __restr
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out[j] = sum_i dz[i][j], rows in order.
-__global__ void k_colsum(const float* __restrict__ dz, int rows, int cols, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    float s = 0.0f;
-    for (int i = 0; i < rows; ++i) s += dz[(int64_t)i * cols + j];
-    out[j] = s;
+// out[j] = sum_i dz[i][j].  A workgroup takes 64 columns (one coalesced
+// row segment per wave load); its 16 waves take the rows i = w, w + 16, ...
+// with four running sums each (rows 64c + w + 16q go to sum q), and the
+// 64 partial sums of a column are added in a fixed order through LDS, so
+// the result depends only on rows and cols: replays give the same bits.
+constexpr int kColsumWaves = 16;
+
+__global__ void __launch_bounds__(64 * kColsumWaves) k_colsum(const float* __restrict__ dz, int rows, int cols,
+                                                               float* __restrict__ out) {
+    __shared__ float part[kColsumWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (j < cols) {
+        int i = w;
+        for (; i + 3 * kColsumWaves < rows; i += 4 * kColsumWaves)
+            for (int q = 0; q < 4; ++q) s[q] += dz[(int64_t)(i + q * kColsumWaves) * cols + j];
+        if (i < rows) s[0] += dz[(int64_t)i * cols + j];
+        if (i + kColsumWaves < rows) s[1] += dz[(int64_t)(i + kColsumWaves) * cols + j];
+        if (i + 2 * kColsumWaves < rows) s[2] += dz[(int64_t)(i + 2 * kColsumWaves) * cols + j];
+    }
+    part[w][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+    __syncthreads();
+    if (w == 0 && j < cols) {
+        float t = 0.0f;
+        for (int v = 0; v < kColsumWaves; ++v) t += part[v][lane];
+        out[j] = t;
+    }
 }
 
 // Adam with bias correction; the step number is *step + 1 (the counter is
@@ -270,7 +291,8 @@ hipError_t backward(hrir_mlp* m, int n, const float* d_t, hipStream_t st) {
         Epi ew{nullptr, nullptr, 0, 0, 0, m->d_g + m->w_off[l], o};
         r = gemm(m, st, true, m->d_act[l], 1, k, dz, o, 1, k, o, n, ew);
         if (r != hipSuccess) break;
-        hipLaunchKernelGGL(k_colsum, dim3(cdiv(o, 256)), dim3(256), 0, st, dz, n, o, m->d_g + m->b_off[l]);
+        hipLaunchKernelGGL(k_colsum, dim3(cdiv(o, 64)), dim3(64 * kColsumWaves), 0, st, dz, n, o,
+                           m->d_g + m->b_off[l]);
         r = hipGetLastError();
         if (r != hipSuccess || l == 0) break;
         // dz_{l-1} = (dz W^T) [act_l > 0]  (n x k, contraction over o)
