@@ -29,19 +29,47 @@ namespace hrir {
 
 constexpr int kMovItem = 256;     // outputs per work item (one quad per lane)
 
+// Filters a tile can need: both ears of every segment it overlaps and of the
+// segment before (its last samples fade into the tile's first segment).
+__host__ __device__ inline int moving_tile_filters(int TB) { return 2 * (TB / kMovItem + 2); }
+
+// LDS floats after the z copies: filter rows, then their positions and gains.
 template <int KP>
-__device__ __forceinline__ void quad_taps(const float* zl, int CS, int H, const int* __restrict__ pp,
-                                          const float* __restrict__ gg, float (&acc)[4]) {
+__host__ __device__ inline int moving_tap_lds(int TB) { return moving_tile_filters(TB) * (1 + 2 * KP); }
+
+// Empty asm over the 4 accumulators that clobbers memory: LDS reads of the
+// next group of taps are not hoisted above it (all of them in flight at once
+// would take 4 VGPRs per tap and cost occupancy).  Emits no instruction.
+__device__ __forceinline__ void pin4(float (&a)[4]) {
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]) : : "memory");
+}
+
+// pp, gg: one filter's taps staged in LDS (every lane reads the same words).
+// Taps in groups of 4 (KP is a multiple of 4), accumulated in tap order.
+template <int KP>
+__device__ __forceinline__ void quad_taps(const float* zl, int CS, int H, const int* pp, const float* gg,
+                                          float (&acc)[4]) {
+    static_assert(KP % 4 == 0, "taps come in groups of 4");
 #pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        const int p = pp[q];
-        const float g = gg[q];
-        const int c = (H - p) & 3;
-        const float4 v = *reinterpret_cast<const float4*>(zl + c * CS + (H - p - c));
-        acc[0] = fmaf(g, v.x, acc[0]);
-        acc[1] = fmaf(g, v.y, acc[1]);
-        acc[2] = fmaf(g, v.z, acc[2]);
-        acc[3] = fmaf(g, v.w, acc[3]);
+    for (int q0 = 0; q0 < KP; q0 += 4) {
+        float4 v[4];
+        float g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // the same word for every lane: keep the tap in scalar registers
+            const int p = __builtin_amdgcn_readfirstlane(pp[q0 + u]);
+            g[u] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(gg[q0 + u])));
+            const int c = (H - p) & 3;
+            v[u] = *reinterpret_cast<const float4*>(zl + c * CS + (H - p - c));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc[0] = fmaf(g[u], v[u].x, acc[0]);
+            acc[1] = fmaf(g[u], v[u].y, acc[1]);
+            acc[2] = fmaf(g[u], v[u].z, acc[2]);
+            acc[3] = fmaf(g[u], v[u].w, acc[3]);
+        }
+        pin4(acc);
     }
 }
 
@@ -57,26 +85,47 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
     extern __shared__ float4 smem4[];
     float* lds = reinterpret_cast<float*>(smem4);
     const TileDesc td = tiles[blockIdx.x];
-    quad_stage<LFP>(td, src, r, lg, TB, lds);
-    const int H = lg - 1, CS = quad_cs(TB, H);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
     const int s = td.job_begin;                                  // source index
     const int tile_len = min(TB, td.out_len - td.t0);
+    // The tile's filters: segments j_lo .. j_hi, both ears.  Their rows are
+    // read before the source is staged and their taps copied into LDS while
+    // the source window is ready, so no work item waits on a chain of
+    // global loads (segment -> filter row -> taps).
+    const int j_first = min(td.t0 / seg_len, n_seg - 1);
+    const int j_lo = max(j_first - 1, 0);
+    const int j_hi = min((td.t0 + tile_len - 1) / seg_len, n_seg - 1);
+    const int n_fl = 2 * (j_hi - j_lo + 1);
+    const int64_t row = (int64_t)s * n_seg;
+    int f_mine = 0;
+    if (tid < n_fl) f_mine = seg_filt[(row + j_lo) * 2 + tid];
+    int* lds_f = reinterpret_cast<int*>(lds + lds_quad_len(TB, lg, LFP));
+    int* lds_p = lds_f + moving_tile_filters(TB);
+    float* lds_g = reinterpret_cast<float*>(lds_p + moving_tile_filters(TB) * KP);
+    quad_stage<LFP>(td, src, r, lg, TB, lds, [&]() {
+        if (tid < n_fl) lds_f[tid] = f_mine;
+        __syncthreads();
+        for (int a = tid; a < n_fl * KP; a += kQThreads) {
+            const int64_t o = (int64_t)lds_f[a / KP] * KP + a % KP;
+            lds_p[a] = P[o];
+            lds_g[a] = Gv[o];
+        }
+    });
+    const int H = lg - 1, CS = quad_cs(TB, H);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int n_items = 2 * ((tile_len + kMovItem - 1) / kMovItem);
     for (int it = wave; it < n_items; it += kQWaves) {
         const int e = it & 1, blk = it >> 1;
         const int t_blk = td.t0 + kMovItem * blk;
         const int j_raw = t_blk / seg_len;
         const int j = min(j_raw, n_seg - 1);
-        const int64_t row = (int64_t)s * n_seg;
-        const int f = seg_filt[(row + j) * 2 + e];
+        const int fi = 2 * (j - j_lo) + e;
         const float* zl = lds + kMovItem * blk + 4 * lane;
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        quad_taps<KP>(zl, CS, H, P + (int64_t)f * KP, Gv + (int64_t)f * KP, acc);
+        quad_taps<KP>(zl, CS, H, lds_p + fi * KP, lds_g + fi * KP, acc);
         if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len) {
-            const int f0 = seg_filt[(row + j - 1) * 2 + e];
             float acc0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            quad_taps<KP>(zl, CS, H, P + (int64_t)f0 * KP, Gv + (int64_t)f0 * KP, acc0);
+            quad_taps<KP>(zl, CS, H, lds_p + (fi - 2) * KP, lds_g + (fi - 2) * KP, acc0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 4 * lane + i;
@@ -259,7 +308,14 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     m->TB = tile;
     m->n_seg = (int)((src_len + seg_len - 1) / seg_len);
     m->out_len = src_len + pv.lf + pv.lg - 2;
-    m->lds = sizeof(float) * (size_t)lds_quad_len(m->TB, pv.lg, pv.lfp);
+    const int rc_lds = with_lf_k(pv.lfp, pv.kp, [&](auto, auto K) -> int {
+        m->lds = sizeof(float) * (size_t)(lds_quad_len(m->TB, pv.lg, pv.lfp) + moving_tap_lds<decltype(K)::value>(m->TB));
+        return HRIR_OK;
+    });
+    if (rc_lds) {
+        free_moving(m);
+        return rc_lds;
+    }
     std::vector<TileDesc> ht;
     for (int s = 0; s < n_src; ++s)
         for (int64_t t0 = 0; t0 < m->out_len; t0 += m->TB)

@@ -32,18 +32,31 @@ __host__ __device__ inline int lds_quad_len(int TB, int lg, int lfp) {
 
 // Stages the tile's source, runs the FIR and writes the four shifted copies
 // of z into lds (ends with a barrier).  H = lg - 1; CS = quad_cs(TB, H).
-template <int LFP>
+// Only the z values the tile's outputs read are formed (a ragged last tile
+// forms fewer); the bounds come from the tile, so in a loop over tiles the
+// compiler cannot hoist them and keep them live across tiles.
+// after_source() runs once the source window is in LDS (after a barrier)
+// and before the FIR: a caller can stage its own tables there, outside the
+// first lds_quad_len floats, while the FIR's inputs are ready.
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+template <int LFP, class Hook = NoHook>
 __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __restrict__ src,
-                                           const float* __restrict__ r, int lg, int TB, float* lds) {
+                                           const float* __restrict__ r, int lg, int TB, float* lds,
+                                           Hook&& after_source = Hook{}) {
     const int tid = threadIdx.x;
     const int H = lg - 1;
-    const int NZ = TB + H + 3;                 // z_win[u], u < NZ, covers every quad read
+    const int tile_len = min(TB, td.out_len - td.t0);
+    const int NZ = tile_len + H + 3;           // z_win[u], u < NZ, covers every quad read
     const int nz8 = round_up(NZ, kZpt);
     const int CS = quad_cs(TB, H);
     float* s_win = lds;
     float* zc = lds;                           // the copies overwrite s_win after the FIR
 
     stage_s<LFP, kQThreads>(td, src, H, nz8, s_win);
+    after_source();
 
     // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)
     float rr[LFP];
@@ -70,8 +83,8 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
         }
     }
     __syncthreads();                            // every read of s_win is done
-    // Zc[m] = z_win[m + c] for m < TB + H; interior groups of 8 without tests
-    const int mlim = TB + H;
+    // Zc[m] = z_win[m + c] for m < tile_len + H; interior groups of 8 without tests
+    const int mlim = tile_len + H;
 #pragma unroll
     for (int ps = 0; ps < kQPass; ++ps) {
         const int u0 = (ps * kQThreads + tid) * kZpt;
