@@ -115,11 +115,13 @@ int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf, int32_t it
  *                of the k-slot filter.
  * hrir_tune_sigma
  *   For each row, the window bandwidth in grid[0..n_grid) (each > 0, +inf
- *   allowed) whose HRIR_D_WINDOW solution at the given lambda and threshold
- *   minimises the spectral distortion of f * g against x (Eq. (17) over the
- *   m bins of a length-m DFT, magnitudes floored at 1e-12 of their maximum);
- *   ties keep the earlier grid entry (Sec. IV-E).  sigma_out host f64[n],
- *   sd_out host f64[n] or null.
+ *   allowed) whose HRIR_D_WINDOW solution minimises the spectral distortion
+ *   of f * g against x (Eq. (17) over the m bins of a length-m DFT,
+ *   magnitudes floored at 1e-12 of their maximum); ties keep the earlier
+ *   grid entry (Sec. IV-E).  The solution for each bandwidth uses the given
+ *   lambda when target_nnze = 0, else the lambda of hrir_sparsify's search
+ *   for at most target_nnze entries (bandwidth tuned at the sparsity the
+ *   filters will have).  sigma_out host f64[n], sd_out host f64[n] or null.
  * Errors: EINVAL (sizes, null pointers, non-finite inputs, bad sigma or
  * lambda), ENOTPD (a support whose columns are dependent).
  * ---------------------------------------------------------------------- */
@@ -131,7 +133,8 @@ int hrir_sparsify(const double* X, int32_t n, int32_t m, const double* f, int32_
                   const double* sigma, const double* lambda, int32_t target_nnze, double threshold, int32_t k,
                   int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out, double* err_db_out);
 int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, const double* grid,
-                    int32_t n_grid, double lambda, double threshold, double* sigma_out, double* sd_out);
+                    int32_t n_grid, double lambda, int32_t target_nnze, double threshold, double* sigma_out,
+                    double* sd_out);
 
 /* ------------------------------------------------------------------------
  * Render plan: the resonance filter and the sparse tap table on the device.

@@ -150,13 +150,18 @@ def lambda_for_nnze(f, x, lg: int, target: int, kind: str = "I", sigma: float = 
     return hi, g_hi
 
 
-def tune_sigma(f, x, lg: int, grid, lam: float = 0.0, thresh: float = THRESH):
+def tune_sigma(f, x, lg: int, grid, lam: float = 0.0, thresh: float = THRESH, target: int = 0):
     """Window bandwidth of D_W minimising the SD (Eq. (17)) of f * g against x
-    over the grid (inf = identity).  Ties keep the earlier grid entry.
+    over the grid (inf = identity).  Each bandwidth's g solves Eq. (14) at
+    lambda = lam, or, with target > 0, at the lambda of lambda_for_nnze
+    (at most `target` entries).  Ties keep the earlier grid entry.
     Returns (sigma, sd, g)."""
     best = None
     for s in grid:
-        g = sparsify(f, x, lg, "W", float(s), lam, thresh)
+        if target > 0:
+            _, g = lambda_for_nnze(f, x, lg, target, "W", float(s), thresh)
+        else:
+            g = sparsify(f, x, lg, "W", float(s), lam, thresh)
         sd = spectral_distortion(x, np.convolve(np.asarray(f, dtype=np.float64), g))
         if best is None or sd < best[1]:
             best = (float(s), sd, g)

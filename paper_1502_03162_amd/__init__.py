@@ -140,7 +140,8 @@ def _load() -> ctypes.CDLL:
         "stream_loadgen": (c_int, [c_void_p, POINTER(StreamLoad), POINTER(StreamLoadStats)]),
         "hrir_sparsify": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, c_int32, P_d, P_d, c_int32, c_double, c_int32,
                                   P_i32, P_f, P_i32, P_d, P_d]),
-        "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_double, P_d, P_d]),
+        "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_int32, c_double,
+                                    P_d, P_d]),
         "spconv_plan_topk": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p]),
         "spconv_plan_read": (c_int, [c_void_p, c_int32, c_int32, P_i32, P_f]),
         "moving_create": (c_int, [c_void_p, c_int32, c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
@@ -266,9 +267,11 @@ def sparsify(X, f, k: int, transform: str = "I", sigma=None, lam=None, target_nn
     return {"p": p, "g": g, "nnze": nnze, "lambda": lam_out, "err_db": err}
 
 
-def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4):
+def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4, target_nnze: int = 0):
     """Per-row window bandwidth from grid minimising spectral distortion
-    (hrir_tune_sigma).  Returns (sigma, sd)."""
+    (hrir_tune_sigma): each bandwidth's solution at lambda = lam, or, with
+    target_nnze > 0, at the searched lambda that keeps at most target_nnze
+    entries.  Returns (sigma, sd)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     f = np.ascontiguousarray(f, dtype=np.float64)
     gr = np.ascontiguousarray(grid, dtype=np.float64)
@@ -276,7 +279,8 @@ def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4):
     sig = np.empty(n)
     sd = np.empty(n)
     _check(_lib.hrir_tune_sigma(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _ptr(gr, c_double), gr.size,
-                                float(lam), float(threshold), _ptr(sig, c_double), _ptr(sd, c_double)))
+                                float(lam), int(target_nnze), float(threshold), _ptr(sig, c_double),
+                                _ptr(sd, c_double)))
     return sig, sd
 
 

@@ -304,8 +304,8 @@ extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double
 }
 
 extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
-                               const double* grid, int32_t n_grid, double lambda, double threshold,
-                               double* sigma_out, double* sd_out) {
+                               const double* grid, int32_t n_grid, double lambda, int32_t target_nnze,
+                               double threshold, double* sigma_out, double* sd_out) {
     hrir::clear_error();
     int rc = hrir::check_common(X, n, m, f, lf, "hrir_tune_sigma");
     if (rc) return rc;
@@ -313,6 +313,7 @@ extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const doub
     for (int u = 0; u < n_grid; ++u)
         if (!(grid[u] > 0.0)) return fail(HRIR_EINVAL, "hrir_tune_sigma: grid[%d]=%g must be > 0", u, grid[u]);
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(HRIR_EINVAL, "hrir_tune_sigma: lambda invalid");
+    if (target_nnze < 0) return fail(HRIR_EINVAL, "hrir_tune_sigma: target_nnze=%d < 0", target_nnze);
     if (!(threshold >= 0.0)) return fail(HRIR_EINVAL, "hrir_tune_sigma: threshold < 0");
     const int lg = m - lf + 1;
     std::vector<hrir::Design> designs(n_grid);
@@ -329,7 +330,10 @@ extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const doub
         for (int u = 0; u < n_grid; ++u) {
             hrir::design_rhs(designs[u], x, c0);
             int nz = 0;
-            const int st = hrir::solve_one(designs[u], c0, lambda, threshold, c, g.data(), &nz);
+            double lam = lambda;
+            const int st = target_nnze > 0
+                               ? hrir::search_lambda(designs[u], c0, target_nnze, threshold, g.data(), &lam, &nz)
+                               : hrir::solve_one(designs[u], c0, lambda, threshold, c, g.data(), &nz);
             if (st) {
                 status[i] = st;
                 return;

@@ -71,6 +71,16 @@ def test_sigma_tuning_matches_oracle(hset):
         assert abs(sd[i] - sd_o) <= 1e-9
 
 
+def test_sigma_tuning_at_target_sparsity_matches_oracle(hset):
+    X, f, lg = hset
+    grid = [20.0, 60.0, math.inf]
+    sig, sd = H.tune_sigma(X, f, grid, target_nnze=6)
+    for i in (0, 13, 27):
+        s_o, sd_o, _ = L.tune_sigma(f, X[i], lg, grid, target=6)
+        assert sig[i] == s_o
+        assert abs(sd[i] - sd_o) <= 1e-9
+
+
 def test_k_slot_cut_keeps_the_largest(hset):
     X, f, lg = hset
     full = H.sparsify(X, f, lg, "I", lam=0.0)
@@ -96,6 +106,8 @@ def test_argument_errors(hset):
         H.sparsify(X, f, 0, "I", lam=0.0)
     with pytest.raises(H.HrirError):
         H.tune_sigma(X, f, [10.0, 0.0])
+    with pytest.raises(H.HrirError):
+        H.tune_sigma(X, f, [10.0], target_nnze=-1)
     bad = X.copy()
     bad[0, 3] = np.nan
     with pytest.raises(H.HrirError):

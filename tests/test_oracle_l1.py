@@ -138,3 +138,20 @@ def test_sigma_tuning_never_worse_than_identity():
         assert s in grid
         s1, sd1, g1 = L.tune_sigma(f, X[i], lg, [math.inf])
         assert s1 == math.inf and np.array_equal(g1, g_id) and sd1 == sd_id
+
+
+def test_sigma_tuning_at_target_sparsity_never_worse_than_identity():
+    """Tuned at the target sparsity (lambda searched per bandwidth), the grid
+    holds the identity (sigma = inf), so the chosen SD is at most the
+    identity's; D_W(inf) reproduces the identity's search exactly."""
+    X, f, lg = _setup()
+    grid = [20.0, 60.0, math.inf]
+    for i in (0, 9, 17):
+        s, sd, g = L.tune_sigma(f, X[i], lg, grid, target=6)
+        _, g_id = L.lambda_for_nnze(f, X[i], lg, 6)
+        sd_id = oracle.spectral_distortion(X[i], np.convolve(f, g_id))
+        assert np.count_nonzero(g) <= 6
+        assert sd <= sd_id + 1e-12
+        s1, sd1, g1 = L.tune_sigma(f, X[i], lg, [math.inf], target=6)
+        assert s1 == math.inf and np.array_equal(g1, g_id) and sd1 == sd_id
+
