@@ -562,7 +562,7 @@ def main():
                     help="also run 3 device copies of 1 GiB (read 1 GiB + write 1 GiB each) to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the renderer runs on one GPU only (the multi-GPU layout is a design note); run with --gpus 1"}))
         sys.exit(2)
 
     import torch
