@@ -66,18 +66,26 @@ __device__ __forceinline__ void epilogue(const Epi& e, int i, int j, float x) {
 }
 
 // C[M][N] = A[M][K] B[K][N]; A(i, k) = A[i sa_r + k sa_c], B(k, j) = B[k sb_r + j sb_c].
-// One wave per 32 x 32 output tile (MFMA 32x32x2).  With gridDim.z > 1 the
-// contraction is split: block z sums k in [z k_chunk, (z + 1) k_chunk) and
-// writes its raw partial tile to ws[z][M][N]; k_splitk_reduce adds the parts
-// in order and applies the epilogue.
-template <class TA>
-__global__ __launch_bounds__(64) void k_gemm(const TA* __restrict__ A, int64_t sa_r, int64_t sa_c,
-                                             const float* __restrict__ B, int64_t sb_r, int64_t sb_c, int M, int N,
-                                             int K, int k_chunk, Epi e, float* __restrict__ ws) {
-    const int lane = threadIdx.x;
+// One workgroup per 32 x 32 output tile (MFMA 32x32x2).  With W = 4 its
+// waves take consecutive quarters of the block's contraction range, so each
+// runs a quarter of the dependent load -> MFMA chain (for launches with few
+// tiles), and their partial tiles are added through LDS in wave order (the
+// same bits on every run); W = 1 when the tiles alone fill the GPU.  With
+// gridDim.z > 1 the contraction is also split over blocks: block z sums k in
+// [z k_chunk, (z + 1) k_chunk) and writes its raw partial tile to
+// ws[z][M][N]; k_splitk_reduce adds the parts in order and applies the
+// epilogue.  k_chunk is a multiple of 16 W.
+template <class TA, int W>
+__global__ __launch_bounds__(64 * W) void k_gemm(const TA* __restrict__ A, int64_t sa_r, int64_t sa_c,
+                                                 const float* __restrict__ B, int64_t sb_r, int64_t sb_c, int M,
+                                                 int N, int K, int k_chunk, Epi e, float* __restrict__ ws) {
+    __shared__ float part[W > 1 ? W : 1][16][64];
+    const int lane = threadIdx.x & 63, w = W > 1 ? (int)(threadIdx.x >> 6) : 0;
     const int row0 = blockIdx.y * 32, col0 = blockIdx.x * 32;
     const int ai = row0 + (lane & 31), bj = col0 + (lane & 31), kk = lane >> 5;
-    const int kb = blockIdx.z * k_chunk, ke = min(K, kb + k_chunk);
+    const int kw = k_chunk / W;
+    const int kb = blockIdx.z * k_chunk + w * kw;
+    const int ke = min(K, kb + kw);
     f32x16 acc = {};
     // eight k-steps per iteration: their loads are issued together, then the MFMAs
     for (int k0 = kb; k0 < ke; k0 += 16) {
@@ -91,16 +99,31 @@ __global__ __launch_bounds__(64) void k_gemm(const TA* __restrict__ A, int64_t s
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
     }
-    // accumulator v of lane l holds C[row0 + (v & 3) + 4 (l >> 5) + 8 (v >> 2)][col0 + (l & 31)]
+    if (W > 1) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
+        for (int v = 0; v < 16; ++v) part[w][v][lane] = acc[v];
+        __syncthreads();
+    }
+    // wave w finishes accumulator entries v = (16 / W) w ... of every lane:
+    // entry v of lane l is C[row0 + (v & 3) + 4 (l >> 5) + 8 (v >> 2)][col0 + (l & 31)]
+#pragma unroll
+    for (int q = 0; q < 16 / W; ++q) {
+        const int v = w * (16 / W) + q;
+        float x;
+        if (W > 1) {
+            x = part[0][v][lane];
+#pragma unroll
+            for (int u = 1; u < W; ++u) x += part[u][v][lane];
+        } else {
+            x = acc[v];
+        }
         const int i = row0 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
         const int j = col0 + (lane & 31);
         if (i >= M || j >= N) continue;
         if (gridDim.z > 1)
-            ws[((int64_t)blockIdx.z * M + i) * N + j] = acc[v];
+            ws[((int64_t)blockIdx.z * M + i) * N + j] = x;
         else
-            epilogue(e, i, j, acc[v]);
+            epilogue(e, i, j, x);
     }
 }
 
@@ -243,20 +266,31 @@ constexpr int kMaxSplits = 16;
 hipError_t gemm(hrir_mlp* m, hipStream_t st, bool a_bf16, const void* A, int64_t sa_r, int64_t sa_c, const float* B,
                 int64_t sb_r, int64_t sb_c, int M, int N, int K, const Epi& e) {
     const int tiles = cdiv(M, 32) * cdiv(N, 32);
+    // four waves per tile while the tiles leave most of the GPU idle
+    const bool quad = tiles < 2048;
+    const int kStep = quad ? 64 : 16;                      // k_chunk granularity: 16 per wave
     int splits = 1;
-    if (tiles < 512 && K >= 256) {
-        splits = std::min<int>(kMaxSplits, std::max(1, K / 128));
+    if (tiles < 256 && K >= 512) {
+        splits = std::min<int>(kMaxSplits, std::max(1, K / 256));
         while (splits > 1 && (int64_t)splits * M * N > m->ws_elems) --splits;
     }
-    const int k_chunk = (cdiv(K, splits) + 15) / 16 * 16;
+    const int k_chunk = (cdiv(K, splits) + kStep - 1) / kStep * kStep;
     splits = cdiv(K, k_chunk);
     const dim3 grid(cdiv(N, 32), cdiv(M, 32), splits);
-    if (a_bf16)
-        hipLaunchKernelGGL(k_gemm<uint16_t>, grid, dim3(64), 0, st, static_cast<const uint16_t*>(A), sa_r, sa_c, B,
-                           sb_r, sb_c, M, N, K, k_chunk, e, m->d_ws);
+    const auto* Ab = static_cast<const uint16_t*>(A);
+    const auto* Af = static_cast<const float*>(A);
+    if (a_bf16 && quad)
+        hipLaunchKernelGGL((k_gemm<uint16_t, 4>), grid, dim3(256), 0, st, Ab, sa_r, sa_c, B, sb_r, sb_c, M, N, K,
+                           k_chunk, e, m->d_ws);
+    else if (a_bf16)
+        hipLaunchKernelGGL((k_gemm<uint16_t, 1>), grid, dim3(64), 0, st, Ab, sa_r, sa_c, B, sb_r, sb_c, M, N, K,
+                           k_chunk, e, m->d_ws);
+    else if (quad)
+        hipLaunchKernelGGL((k_gemm<float, 4>), grid, dim3(256), 0, st, Af, sa_r, sa_c, B, sb_r, sb_c, M, N, K,
+                           k_chunk, e, m->d_ws);
     else
-        hipLaunchKernelGGL(k_gemm<float>, grid, dim3(64), 0, st, static_cast<const float*>(A), sa_r, sa_c, B, sb_r,
-                           sb_c, M, N, K, k_chunk, e, m->d_ws);
+        hipLaunchKernelGGL((k_gemm<float, 1>), grid, dim3(64), 0, st, Af, sa_r, sa_c, B, sb_r, sb_c, M, N, K, k_chunk,
+                           e, m->d_ws);
     if (splits > 1)
         hipLaunchKernelGGL(k_splitk_reduce, dim3(std::min(cdiv((int64_t)M * N, 256), 1024)), dim3(256), 0, st, m->d_ws,
                            splits, M, N, e);
