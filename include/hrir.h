@@ -333,8 +333,11 @@ void fftola_destroy(hrir_fft* plan);
  *     d_out     device f32: block i writes m samples of the left ear
  *               (filt_l) at out_off and m of the right ear (filt_r) at
  *               out_off + m; m = n, or lf + lg - 2 for a flush block.
- *     The job table is staged through pinned host memory (double buffered),
- *     so the call returns after enqueueing and jobs may be reused at once.
+ *     The job table is copied into pinned, coherent host memory (double
+ *     buffered) that the kernel reads in place -- no copy command precedes
+ *     the launch -- so the call returns after enqueueing and jobs may be
+ *     reused at once; a call waits only for the kernel of the call before
+ *     the previous one (it reads the same half).
  * Errors: EINVAL (ranges, a stream twice in one call, buffers too small),
  * EDEVICE.
  * ---------------------------------------------------------------------- */

@@ -109,9 +109,10 @@ struct hrir_streams {
     int max_streams = 0, hist_stride = 0, n_filt = 0, device = 0;
     int call_id = 0;
     float* d_hist = nullptr;
-    // job tables: pinned host staging, device copy (double buffered)
+    // job tables (double buffered) in pinned, coherent host memory that the
+    // kernel reads in place: a launch needs no copy command before it
     BJob* h_jobs[2] = {nullptr, nullptr};
-    BJob* d_jobs[2] = {nullptr, nullptr};
+    BJob* d_jobs[2] = {nullptr, nullptr};   // device addresses of h_jobs
     int32_t* h_slots = nullptr;
     int32_t* d_slots = nullptr;
     hipEvent_t used[2] = {nullptr, nullptr};
@@ -167,7 +168,6 @@ void free_streams(hrir_streams* s) {
     (void)hipFree(s->d_hist);
     for (int i = 0; i < 2; ++i) {
         (void)hipHostFree(s->h_jobs[i]);
-        (void)hipFree(s->d_jobs[i]);
         if (s->used[i]) (void)hipEventDestroy(s->used[i]);
     }
     (void)hipHostFree(s->h_slots);
@@ -208,8 +208,8 @@ extern "C" int block_streams_create(const hrir_plan* plan, int32_t max_streams, 
     s->cap = max_streams;
     hipError_t e = hipMalloc(&s->d_hist, (size_t)max_streams * s->hist_stride * sizeof(float));
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipHostMalloc(&s->h_jobs[i], (size_t)s->cap * sizeof(BJob), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc(&s->d_jobs[i], (size_t)s->cap * sizeof(BJob));
+        e = hipHostMalloc(&s->h_jobs[i], (size_t)s->cap * sizeof(BJob), hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_jobs[i]), s->h_jobs[i], 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s->used[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipHostMalloc(&s->h_slots, (size_t)max_streams * sizeof(int32_t), hipHostMallocDefault);
@@ -294,7 +294,8 @@ extern "C" int block_render(hrir_streams* s, const float* d_in, int64_t in_elems
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int b = s->cur;
     s->cur ^= 1;
-    // the staging half is free once the copy that last read it has run
+    // this half of the job table is free once the kernel that last read it
+    // (two calls ago) has finished
     hipError_t e = hipEventSynchronize(s->used[b]);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
     for (int i = 0; i < n_jobs; ++i) {
@@ -302,11 +303,9 @@ extern "C" int block_render(hrir_streams* s, const float* d_in, int64_t in_elems
         s->h_jobs[b][i] = BJob{j.stream_id, j.n, j.filt_l, j.filt_r, (j.flags & BLOCK_FLUSH) ? kJobFlush : 0, 0,
                                j.in_off, j.out_off};
     }
-    e = hipMemcpyAsync(s->d_jobs[b], s->h_jobs[b], sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipEventRecord(s->used[b], st);
-    if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
     const float* din = d_in ? d_in : d_out;   // flush-only calls read no input
     e = block_enqueue(s, din, s->d_jobs[b], nullptr, n_jobs, n_jobs, max_m, d_out, st);
+    if (e == hipSuccess) e = hipEventRecord(s->used[b], st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_render: %s", hipGetErrorString(e));
     return HRIR_OK;
 }
