@@ -73,8 +73,8 @@ __host__ __device__ inline int lds_z_len(int TB, int lg) { return round_up(TB + 
 // multiple of 8).  Ends with a barrier.
 template <int LFP, int NT = kThreads>
 __device__ __forceinline__ void stage_s(const TileDesc& td, const float* __restrict__ src, int H, int nz8,
-                                        float* s_win) {
-    const int tid = threadIdx.x;
+                                        float* s_win,
+                                        int tid) {
     const int ns = nz8 + LFP + 4;
     // 1. stage s[sbase + i], zero outside [0, src_len).  Interior tiles use
     //    16-byte loads (any dword alignment), kStageV per thread in flight
@@ -116,7 +116,7 @@ __device__ __forceinline__ void stage_z(const TileDesc& td, const float* __restr
                                         float* z_win) {
     const int tid = threadIdx.x;
     const int nz8 = round_up(TB + H, kZpt);
-    stage_s<LFP>(td, src, H, nz8, s_win);
+    stage_s<LFP>(td, src, H, nz8, s_win, (int)threadIdx.x);
 
     // 2. z_win[u] = z[t0 - H + u] = sum_n r[n] s_win[u + LFP - 1 - n]
     float rr[LFP];

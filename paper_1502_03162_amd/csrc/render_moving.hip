@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
     int* lds_f = reinterpret_cast<int*>(lds + lds_quad_len(TB, lg, LFP));
     int* lds_p = lds_f + moving_tile_filters(TB);
     float* lds_g = reinterpret_cast<float*>(lds_p + moving_tile_filters(TB) * KP);
-    quad_stage<LFP>(td, src, r, lg, TB, lds, [&]() {
+    quad_stage<LFP>(td, src, r, lg, TB, lds, tid, [&]() {
         if (tid < n_fl) lds_f[tid] = f_mine;
         __syncthreads();
         for (int a = tid; a < n_fl * KP; a += kQThreads) {

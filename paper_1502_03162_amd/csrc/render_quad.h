@@ -42,11 +42,13 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
+// tid: this thread's index in the workgroup (a persistent caller passes one
+// the compiler cannot see as loop-invariant, so that nothing derived from
+// it is hoisted out of its loop over tiles).
 template <int LFP, class Hook = NoHook>
 __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __restrict__ src,
-                                           const float* __restrict__ r, int lg, int TB, float* lds,
+                                           const float* __restrict__ r, int lg, int TB, float* lds, int tid,
                                            Hook&& after_source = Hook{}) {
-    const int tid = threadIdx.x;
     const int H = lg - 1;
     const int tile_len = min(TB, td.out_len - td.t0);
     const int NZ = tile_len + H + 3;           // z_win[u], u < NZ, covers every quad read
@@ -55,7 +57,7 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
     float* s_win = lds;
     float* zc = lds;                           // the copies overwrite s_win after the FIR
 
-    stage_s<LFP, kQThreads>(td, src, H, nz8, s_win);
+    stage_s<LFP, kQThreads>(td, src, H, nz8, s_win, tid);
     after_source();
 
     // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)

@@ -36,9 +36,8 @@ template <int LFP, int KP>
 __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float* __restrict__ src,
                                                  const JobDesc* __restrict__ jobs, const float* __restrict__ r,
                                                  const int* __restrict__ P, const float* __restrict__ Gv,
-                                                 float* __restrict__ out, int lg, int TB, float* lds) {
-    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds);
-    const int tid = threadIdx.x;
+                                                 float* __restrict__ out, int lg, int TB, float* lds, int tid) {
+    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid);
     const int H = lg - 1;
     const int CS = quad_cs(TB, H);
     const float* zc = lds;
@@ -137,12 +136,15 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_quad(const float* __res
                                                                      float* __restrict__ out, int lg, int TB) {
     extern __shared__ float4 smem4[];
     const TileDesc td = tiles[blockIdx.x];
-    render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4));
+    render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4), (int)threadIdx.x);
 }
 
 // Persistent variant over the device tile counter (see k_render_persistent).
+// For lf <= 32 it is held to 64 VGPRs (8 waves per SIMD, 4 tiles per CU like
+// the one-tile kernel) at the cost of a few spilled dwords per lane; with
+// 73 VGPRs it would fit 3 tiles per CU, and the loop measured 2-5 % slower.
 template <int LFP, int KP>
-__global__ __launch_bounds__(kQThreads, 4) void k_render_quad_persistent(
+__global__ __launch_bounds__(kQThreads, LFP <= 32 ? 8 : 4) void k_render_quad_persistent(
     const float* __restrict__ src, const TileDesc* __restrict__ tiles, int n_tiles,
     const JobDesc* __restrict__ jobs, const float* __restrict__ r, const int* __restrict__ P,
     const float* __restrict__ Gv, float* __restrict__ out, int lg, int TB, int* __restrict__ ctr) {
@@ -154,8 +156,17 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_quad_persistent(
         const int t = s_next;
         __syncthreads();
         if (t >= n_tiles) break;
+        // s_next is read again after the barrier: the same value (thread 0
+        // writes it only after the tile's last barrier), but the compiler
+        // cannot prove it, so the thread index below varies per tile and
+        // nothing derived from it is hoisted out of this loop -- hoisted
+        // values stay live across tiles and cost occupancy
+        const int zero = s_next - t;
+        const int tid = (int)threadIdx.x + zero;
+        const int z = __builtin_amdgcn_readfirstlane(zero);
         const TileDesc td = tiles[t];
-        render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4));
+        render_tile_quad<LFP, KP>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
+                                  reinterpret_cast<float*>(smem4), tid);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
