@@ -382,8 +382,13 @@ void block_streams_destroy(hrir_streams* streams);
  *                generation ring (EINVAL if it cannot hold two generations
  *                of one maximal block).  flags: STREAM_DIRECT_LAUNCH sizes
  *                each launch to its batch (one workgroup per block) instead
- *                of replaying a HIP graph of a persistent launch.  Starts a
- *                loop thread and a completion thread on the current device.
+ *                of replaying a HIP graph of a persistent launch;
+ *                STREAM_ZERO_COPY keeps the generation ring (job tables,
+ *                input blocks, outputs) in pinned, coherent host memory
+ *                that the kernel reads and writes in place -- a launch needs
+ *                no copy commands, and hbm_budget then bounds the
+ *                histories plus that pinned ring.  Starts a loop thread and
+ *                a completion thread on the current device.
  * stream_submit  copies n samples (1..4096) of host_block; the caller keeps
  *                its buffer.  filt_l/filt_r are the block's left/right
  *                filters (a direction change takes effect at the block
@@ -415,6 +420,7 @@ void block_streams_destroy(hrir_streams* streams);
  * saw its output in host memory.
  * ---------------------------------------------------------------------- */
 #define STREAM_DIRECT_LAUNCH 1
+#define STREAM_ZERO_COPY 2
 #define STREAM_RESULT_TAIL 1
 
 typedef struct hrir_server hrir_server;

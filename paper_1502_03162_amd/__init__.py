@@ -54,6 +54,7 @@ assert BLOCK_JOB_DTYPE.itemsize == ctypes.sizeof(BlockJob)
 
 
 STREAM_DIRECT_LAUNCH = 1
+STREAM_ZERO_COPY = 2
 STREAM_RESULT_TAIL = 1
 
 

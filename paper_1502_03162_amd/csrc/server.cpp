@@ -15,8 +15,11 @@
 //   wait for the previous generation's kernel (stream histories),
 //   block kernel (persistent grid from a HIP graph, or one workgroup per job),
 //   copy outputs device -> host pinned memory, record the done event.
-// Copies of one generation overlap the kernel of the other.  A completion
-// thread turns done events into results, handed out by stream_poll.
+// Copies of one generation overlap the kernel of the other.  With
+// STREAM_ZERO_COPY the ring lives in pinned, coherent host memory that the
+// kernel reads and writes in place: a generation is the wait and the launch.
+// A completion thread turns done events into results, handed out by
+// stream_poll.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -229,8 +232,10 @@ int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, i
 // generation's kernel event (null for the first).
 hipError_t launch_gen(hrir_server* s, Gen& g, hipStream_t st, hipEvent_t prev) {
     *g.h_hdr = g.n_jobs;
-    hipError_t e = hipMemcpyAsync(g.d_hdr, g.h_hdr, 64 + sizeof(BJob) * (size_t)g.n_jobs, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && g.in_used)
+    const bool zc = (s->flags & STREAM_ZERO_COPY) != 0;     // the kernel reads the host tables in place
+    hipError_t e = hipSuccess;
+    if (!zc) e = hipMemcpyAsync(g.d_hdr, g.h_hdr, 64 + sizeof(BJob) * (size_t)g.n_jobs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g.in_used && !zc)
         e = hipMemcpyAsync(g.d_in, g.h_in, sizeof(float) * (size_t)g.in_used, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && prev) e = hipStreamWaitEvent(st, prev, 0);
     if (e == hipSuccess) {
@@ -240,7 +245,7 @@ hipError_t launch_gen(hrir_server* s, Gen& g, hipStream_t st, hipEvent_t prev) {
             e = block_enqueue(s->streams, g.d_in, g.d_jobs, nullptr, g.n_jobs, g.n_jobs, g.max_m, g.d_out, st);
     }
     if (e == hipSuccess) e = hipEventRecord(g.ev_kernel, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !zc)
         e = hipMemcpyAsync(g.h_out, g.d_out, sizeof(float) * 2 * (size_t)g.out_used, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(g.ev_done, st);
     return e;
@@ -351,9 +356,11 @@ void free_server(hrir_server* s) {
         (void)hipHostFree(g.h_hdr);
         (void)hipHostFree(g.h_in);
         (void)hipHostFree(g.h_out);
-        (void)hipFree(g.d_hdr);
-        (void)hipFree(g.d_in);
-        (void)hipFree(g.d_out);
+        if (!(s->flags & STREAM_ZERO_COPY)) {      // else the d_ pointers alias the host buffers
+            (void)hipFree(g.d_hdr);
+            (void)hipFree(g.d_in);
+            (void)hipFree(g.d_out);
+        }
     }
     for (hipStream_t& x : s->st)
         if (x) (void)hipStreamDestroy(x);
@@ -370,7 +377,8 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
     *out = nullptr;
     if (max_streams < 1 || max_streams > (1 << 20))
         return fail(HRIR_EINVAL, "stream_open: max_streams=%d outside [1, 2^20]", max_streams);
-    if (flags & ~STREAM_DIRECT_LAUNCH) return fail(HRIR_EINVAL, "stream_open: unknown flags 0x%x", flags);
+    if (flags & ~(STREAM_DIRECT_LAUNCH | STREAM_ZERO_COPY))
+        return fail(HRIR_EINVAL, "stream_open: unknown flags 0x%x", flags);
     int32_t shp[3];
     int rc = spconv_plan_shape(plan, shp);
     if (rc) return rc;
@@ -419,13 +427,22 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
     const size_t hdr_bytes = 64 + sizeof(BJob) * (size_t)s->cap_jobs;
     const int max_m = (int)min_cap;
+    const bool zc = (flags & STREAM_ZERO_COPY) != 0;
+    const unsigned host_flags = zc ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
+    auto device_view = [](void* h, void** d) { return hipHostGetDevicePointer(d, h, 0); };
     for (Gen& g : s->gens) {
-        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_hdr, hdr_bytes, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_in, sizeof(float) * (size_t)cap, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_out, sizeof(float) * 2 * (size_t)cap, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void**)&g.d_hdr, hdr_bytes);
-        if (e == hipSuccess) e = hipMalloc((void**)&g.d_in, sizeof(float) * (size_t)cap);
-        if (e == hipSuccess) e = hipMalloc((void**)&g.d_out, sizeof(float) * 2 * (size_t)cap);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_hdr, hdr_bytes, host_flags);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_in, sizeof(float) * (size_t)cap, host_flags);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_out, sizeof(float) * 2 * (size_t)cap, host_flags);
+        if (zc) {
+            if (e == hipSuccess) e = device_view(g.h_hdr, (void**)&g.d_hdr);
+            if (e == hipSuccess) e = device_view(g.h_in, (void**)&g.d_in);
+            if (e == hipSuccess) e = device_view(g.h_out, (void**)&g.d_out);
+        } else {
+            if (e == hipSuccess) e = hipMalloc((void**)&g.d_hdr, hdr_bytes);
+            if (e == hipSuccess) e = hipMalloc((void**)&g.d_in, sizeof(float) * (size_t)cap);
+            if (e == hipSuccess) e = hipMalloc((void**)&g.d_out, sizeof(float) * 2 * (size_t)cap);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_kernel, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_done, hipEventDisableTiming);
         if (e != hipSuccess) break;

@@ -132,7 +132,7 @@ def _check_oracle(out, scripts, r, p, g, lg):
     return worst
 
 
-@pytest.mark.parametrize("flags", [0, 1], ids=["graph", "direct"])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3], ids=["graph", "direct", "zero_copy_graph", "zero_copy_direct"])
 def test_mix_matches_oracle_and_alone(dev, flags):
     h = H()
     lf, lg, k, F = 32, 169, 16, 40
@@ -154,19 +154,22 @@ def test_mix_matches_oracle_and_alone(dev, flags):
     plan.close()
 
 
-def test_graph_and_direct_launch_agree_bitwise(dev):
+def test_launch_forms_agree_bitwise(dev):
+    """Graph or direct launch, device ring or zero-copy host ring: the same
+    bits for every stream."""
     h = H()
     lf, lg, k, F = 32, 169, 16, 20
     r, p, g = _taps(12, lf, lg, k, F)
     plan = h.Plan(r, p, g, lg)
     scripts = {s: _script(2000 + s, F, n_blocks=5) for s in range(12)}
     outs = []
-    for flags in (0, h.STREAM_DIRECT_LAUNCH):
+    for flags in (0, h.STREAM_DIRECT_LAUNCH, h.STREAM_ZERO_COPY, h.STREAM_ZERO_COPY | h.STREAM_DIRECT_LAUNCH):
         srv = h.Server(plan, max_streams=16, flags=flags)
         outs.append(_drive(srv, scripts, seed=3))
         srv.close()
-    for s in scripts:
-        assert np.array_equal(outs[0][s][0], outs[1][s][0]) and np.array_equal(outs[0][s][1], outs[1][s][1])
+    for o in outs[1:]:
+        for s in scripts:
+            assert np.array_equal(outs[0][s][0], o[s][0]) and np.array_equal(outs[0][s][1], o[s][1])
     plan.close()
 
 
@@ -184,7 +187,8 @@ def test_shapes_match_oracle(dev, lf, lg, k):
     plan.close()
 
 
-def test_backpressure_small_budget(dev):
+@pytest.mark.parametrize("flags", [0, 2], ids=["device_ring", "zero_copy"])
+def test_backpressure_small_budget(dev, flags):
     """A budget of exactly two generations of one maximal block: blocks are
     refused (EAGAIN) until polls free generations, and every result is
     still exact."""
@@ -195,8 +199,8 @@ def test_backpressure_small_budget(dev):
     hist = ms * 200 * 4                      # round_up(lf - 1 + lg - 1, 4) floats per stream
     per_gen = 64 + 32 * ms + 12 * 4096
     with pytest.raises(h.HrirError):
-        h.Server(plan, max_streams=ms, hbm_budget=hist + 2 * per_gen - 1)
-    srv = h.Server(plan, max_streams=ms, hbm_budget=hist + 2 * per_gen)
+        h.Server(plan, max_streams=ms, hbm_budget=hist + 2 * per_gen - 1, flags=flags)
+    srv = h.Server(plan, max_streams=ms, hbm_budget=hist + 2 * per_gen, flags=flags)
     info = srv.info()
     assert info["generations"] == 2 and info["gen_samples"] == 4096
     scripts = {s: _script(4000 + s, F, n_blocks=5, lo=900, hi=1100) for s in range(ms)}
