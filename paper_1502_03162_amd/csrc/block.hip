@@ -115,6 +115,7 @@ struct hrir_streams {
     BJob* d_jobs[2] = {nullptr, nullptr};   // device addresses of h_jobs
     int32_t* h_slots = nullptr;
     int32_t* d_slots = nullptr;
+    hipEvent_t slots_used = nullptr;     // after the last reset kernel (reads d_slots)
     hipEvent_t used[2] = {nullptr, nullptr};
     int cap = 0, cur = 0;
     std::vector<int> seen;               // per-call uniqueness check
@@ -172,6 +173,7 @@ void free_streams(hrir_streams* s) {
     }
     (void)hipHostFree(s->h_slots);
     (void)hipFree(s->d_slots);
+    if (s->slots_used) (void)hipEventDestroy(s->slots_used);
     delete s;
 }
 
@@ -214,6 +216,7 @@ extern "C" int block_streams_create(const hrir_plan* plan, int32_t max_streams, 
     }
     if (e == hipSuccess) e = hipHostMalloc(&s->h_slots, (size_t)max_streams * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&s->d_slots, (size_t)max_streams * sizeof(int32_t));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->slots_used, hipEventDisableTiming);
     if (e == hipSuccess) {
         // all histories start at zero
         for (int i = 0; i < max_streams; ++i) s->h_slots[i] = i;
@@ -248,8 +251,9 @@ extern "C" int block_streams_reset(hrir_streams* s, const int32_t* slots, int32_
         if (slots[i] < 0 || slots[i] >= s->max_streams)
             return fail(HRIR_EINVAL, "block_streams_reset: slot %d out of range", slots[i]);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    // the staging buffer may still be read by an earlier reset on this stream
-    hipError_t e = hipStreamSynchronize(st);
+    // the slot lists (host staging and device copy) are free once the last
+    // reset kernel, on whatever stream, has run
+    hipError_t e = hipEventSynchronize(s->slots_used);
     if (e == hipSuccess) {
         std::memcpy(s->h_slots, slots, sizeof(int32_t) * n);
         e = hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
@@ -258,6 +262,7 @@ extern "C" int block_streams_reset(hrir_streams* s, const int32_t* slots, int32_
         hipLaunchKernelGGL(k_block_reset, dim3(n), dim3(64), 0, st, s->d_hist, s->hist_stride, s->d_slots, n);
         e = hipGetLastError();
     }
+    if (e == hipSuccess) e = hipEventRecord(s->slots_used, st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "block_streams_reset: %s", hipGetErrorString(e));
     return HRIR_OK;
 }
