@@ -171,8 +171,9 @@ def bench_latency(H, torch, dev, fac, r, lg, args):
     """Block latency: 1,024 streams; each launch renders one block of
     U{64..1024} samples per stream (both ears of a random direction) with the
     stream histories on the device.  HIP events bracket each block_render
-    call (its host-side check and job-table upload, then the kernel); job
-    tables are built before the bracket.  Inputs are resident in HBM."""
+    call (its host-side check, the job table written into pinned memory that
+    the kernel reads, then the kernel); job tables are built before the
+    bracket.  Inputs are resident in HBM."""
     import synth
     n_streams, ticks = 1024, args.latency_ticks
     rng = np.random.default_rng(77)
@@ -218,8 +219,9 @@ def bench_latency(H, torch, dev, fac, r, lg, args):
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "gpu_samples_per_s": samples / (lat.sum() * 1e-3),
            "wall_samples_per_s": samples / wall,
-           "note": "per launch: HIP events around block_render (host-side check and job-table upload, then the "
-                   "kernel); wall_samples_per_s also includes building the job tables in Python"}
+           "note": "per launch: HIP events around block_render (host-side check, the job table written into "
+                   "pinned memory the kernel reads, then the kernel); wall_samples_per_s also includes building "
+                   "the job tables in Python"}
     log(f"block latency: p50 {res['p50_ms'] * 1e3:.1f} us, p99 {res['p99_ms'] * 1e3:.1f} us, "
         f"{res['gpu_samples_per_s']:.3g} output samples/s on the GPU")
     return res
