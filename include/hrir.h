@@ -597,6 +597,8 @@ typedef struct {
     double p50_server_ms, p99_server_ms;
     double p99_admit_ms, max_admit_ms;     /* arrival -> admitted by stream_submit */
     double p99_collect_ms, max_collect_ms; /* done -> collected by the polling thread */
+    double max_wait_ms;      /* longest submit -> launch of its generation */
+    double max_launch_ms;    /* longest launch -> done of a generation */
 } stream_load_stats;
 
 int stream_loadgen(hrir_server* server, const stream_load* cfg, stream_load_stats* stats);

@@ -79,7 +79,8 @@ class StreamLoadStats(ctypes.Structure):
                 ("submit_s", c_double), ("wall_s", c_double), ("mean_batch", c_double), ("p50_ms", c_double),
                 ("p99_ms", c_double), ("max_ms", c_double), ("p50_server_ms", c_double),
                 ("p99_server_ms", c_double), ("p99_admit_ms", c_double), ("max_admit_ms", c_double),
-                ("p99_collect_ms", c_double), ("max_collect_ms", c_double)]
+                ("p99_collect_ms", c_double), ("max_collect_ms", c_double), ("max_wait_ms", c_double),
+                ("max_launch_ms", c_double)]
 
 
 def _preload_torch_fft():

@@ -55,7 +55,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     std::atomic<bool> submit_done{false};
     std::atomic<int64_t> give_up_ns{INT64_MAX};      // set once submission ends
     std::atomic<int> poll_error{0};
-    int64_t out_samples = 0, n_done = 0, t_last_done = 0;
+    int64_t out_samples = 0, n_done = 0, t_last_done = 0, max_wait = 0, max_gpu = 0;
 
     std::thread poller([&] {
         std::vector<hrir_result> res(4096);
@@ -71,6 +71,8 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
                 lat.push_back(r.t_done_ns - arrival[(size_t)r.tag]);
                 lat_srv.push_back(r.t_done_ns - r.t_submit_ns);
                 collect.push_back(t_got - r.t_done_ns);
+                max_wait = std::max(max_wait, r.t_launch_ns - r.t_submit_ns);
+                max_gpu = std::max(max_gpu, r.t_done_ns - r.t_launch_ns);
                 out_samples += 2 * (int64_t)r.n;
                 t_last_done = std::max(t_last_done, r.t_done_ns);
             }
@@ -186,5 +188,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     st->max_admit_ms = pct(adm, 1.0);
     st->p99_collect_ms = pct(collect, 0.99);
     st->max_collect_ms = pct(collect, 1.0);
+    st->max_wait_ms = (double)max_wait * 1e-6;
+    st->max_launch_ms = (double)max_gpu * 1e-6;
     return HRIR_OK;
 }

@@ -54,7 +54,6 @@ struct Gen {
     int64_t seq = -1;
     GenState state = kFree;
     int n_jobs = 0, max_m = 0, remaining = 0;
-    int writers = 0;                       // submissions still copying their block in
     bool failed = false;                   // its launch failed: no results
     int64_t in_used = 0, out_used = 0;     // input floats; output samples per ear
     int64_t t_launch = 0, t_done = 0;
@@ -130,7 +129,6 @@ void open_gen(hrir_server* s, int64_t seq) {
     g.in_used = 0;
     g.out_used = 0;
     g.remaining = 0;
-    g.writers = 0;
     g.failed = false;
     g.tag.clear();
     g.t_submit.clear();
@@ -173,13 +171,13 @@ int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
 }
 
 // Wakes the loop thread when generation q has just become launchable (it
-// is the next to launch, holds a job, no copy into it is under way and a
-// device slot is free).  Every other change that can make it launchable
-// notifies on its own (a completion frees a slot; close; an error), so a
-// submission that does not complete this condition wakes nobody: the loop
-// thread is not woken once per block.  Lock held.
+// is the next to launch, holds its first job and a device slot is free).
+// Every other change that can make it launchable notifies on its own (a
+// completion frees a slot; close; an error), so a submission that does not
+// complete this condition wakes nobody: the loop thread is not woken once
+// per block.  Lock held.
 void wake_dispatcher(hrir_server* s, int64_t q) {
-    if (q == s->next_launch && s->gen(q).n_jobs > 0 && s->gen(q).writers == 0 && s->next_launch - s->next_done < kDepth)
+    if (q == s->next_launch && s->gen(q).n_jobs > 0 && s->next_launch - s->next_done < kDepth)
         s->cv_work.notify_one();
 }
 
@@ -187,44 +185,27 @@ int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, i
                 uint64_t tag, bool end, const char* fn) {
     const int m = end ? s->tail : n;
     const int64_t n_in = end ? 0 : n;
-    Gen* gp = nullptr;
-    int64_t in_off = 0, gq = -1;
-    {
-        // reserve the job and its input space; the block is copied after the
-        // lock is released (the loop thread launches a generation only when
-        // no copy into it is under way)
-        auto lk = lock_short(s->mu);
-        if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
-        if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
-        const int64_t q = place(s, stream, m, n_in);
-        if (q < 0) {
-            ++s->n_eagain;
-            return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
-        }
-        Gen& g = s->gen(q);
-        const int i = g.n_jobs++;
-        gq = q;
-        in_off = g.in_used;
-        g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, in_off,
-                           2 * g.out_used};
-        g.in_used += n_in;
-        g.out_used += m;
-        g.max_m = std::max(g.max_m, m);
-        g.tag.push_back(tag);
-        g.t_submit.push_back(now_ns());
-        s->last_seq[stream] = q;
-        if (n_in) {
-            ++g.writers;
-            gp = &g;
-        } else if (i == 0) {
-            wake_dispatcher(s, q);
-        }
+    auto lk = lock_short(s->mu);
+    if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
+    if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
+    const int64_t q = place(s, stream, m, n_in);
+    if (q < 0) {
+        ++s->n_eagain;
+        return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
     }
-    if (gp) {
-        std::memcpy(gp->h_in + in_off, block, sizeof(float) * (size_t)n_in);
-        auto lk = lock_short(s->mu);
-        if (--gp->writers == 0) wake_dispatcher(s, gq);
-    }
+    Gen& g = s->gen(q);
+    const int i = g.n_jobs++;
+    const int64_t in_off = g.in_used;
+    g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, in_off,
+                       2 * g.out_used};
+    if (n_in) std::memcpy(g.h_in + in_off, block, sizeof(float) * (size_t)n_in);
+    g.in_used += n_in;
+    g.out_used += m;
+    g.max_m = std::max(g.max_m, m);
+    g.tag.push_back(tag);
+    g.t_submit.push_back(now_ns());
+    s->last_seq[stream] = q;
+    if (i == 0) wake_dispatcher(s, q);
     return HRIR_OK;
 }
 
@@ -260,7 +241,7 @@ void dispatcher_main(hrir_server* s) {
             if (s->err_code) return true;
             const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
             if (s->closing && !ready) return true;
-            return ready && s->gen(s->next_launch).writers == 0 && s->next_launch - s->next_done < kDepth;
+            return ready && s->next_launch - s->next_done < kDepth;
         });
         const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
         if (s->err_code || (s->closing && !ready)) {
