@@ -145,3 +145,36 @@ def test_moving_tile_lengths_agree_bitwise(dev):
     with pytest.raises(h.HrirError):
         h.Moving(plan, n_src, n, seg, fade, 300)
     plan.close()
+
+
+def test_full_size_moving_config(dev):
+    """The moving-source workload at full size in the benchmark's launch
+    shape: 128 pink sources of 262,144 samples, a direction every 512
+    samples with a 64-sample crossfade, K = 16, tile 2048; 6 sources (both
+    ears, every sample) against the oracle."""
+    import torch
+    h = H()
+    n_src, n, seg, fade, lf, lg, k, F = 128, 262144, 512, 64, 32, 169, 16, 2500
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(lf).astype(np.float32)
+    p, g = synth.random_taps(12, F, k, lg, nnz_min=8)
+    plan = h.Plan(r, p, g, lg)
+    mv = h.Moving(plan, n_src, n, seg, fade, 2048)
+    seg_filt = rng.integers(0, F, (n_src, mv.n_seg, 2)).astype(np.int32)
+    srcs = np.stack([synth.pink(900 + i, n) for i in range(n_src)])
+    stride = (mv.out_len + 63) // 64 * 64
+    src = torch.from_numpy(srcs.reshape(-1)).to(dev)
+    out = torch.full((2 * n_src * stride,), float("nan"), device=dev)
+    mv.render(src, seg_filt, out, stride)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for s in (0, 1, 37, 64, 100, 127):
+        rows = out[2 * s * stride:(2 * s + 2) * stride].cpu().numpy().reshape(2, stride)
+        for e in range(2):
+            ref = oracle.moving_render(r, srcs[s], p, g, lg, seg_filt[s, :, e], seg, fade)
+            worst = max(worst, oracle.rel_l2(rows[e, :mv.out_len], ref))
+    assert worst <= TOL, worst
+    mv.close()
+    plan.close()
+    del out, src
+    torch.cuda.empty_cache()

@@ -173,6 +173,26 @@ def test_launch_forms_agree_bitwise(dev):
     plan.close()
 
 
+def test_full_size_streams(dev):
+    """The serving workload's scale in the benchmark's launch form: 1,024
+    streams of blocks U{64..1024} over a 1,250-direction tap table, K = 16,
+    graph launch; every stream driven, 128 of them checked against the
+    oracle."""
+    h = H()
+    lf, lg, k, F, ms = 32, 169, 16, 2500, 1024
+    r, p, g = _taps(17, lf, lg, k, F)
+    plan = h.Plan(r, p, g, lg)
+    scripts = {s: _script(9000 + s, F, n_blocks=3, lo=64, hi=1024) for s in range(ms)}
+    srv = h.Server(plan, max_streams=ms, hbm_budget=1 << 30)
+    out = _drive(srv, scripts, seed=9, deadline_s=120.0)
+    info = srv.info()
+    srv.close()
+    assert info["results"] == 4 * ms
+    checked = {s: scripts[s] for s in range(0, ms, 8)}
+    _check_oracle({s: out[s] for s in checked}, checked, r, p, g, lg)
+    plan.close()
+
+
 @pytest.mark.parametrize("lf,lg,k", [(1, 1, 1), (5, 2, 2), (64, 2048, 64), (17, 40, 3)])
 def test_shapes_match_oracle(dev, lf, lg, k):
     h = H()

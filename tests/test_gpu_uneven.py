@@ -63,3 +63,45 @@ def test_uneven_mix_parity_and_shapes(dev, tmp_path):
     assert len(json.load(open(cache))) == 2
     assert np.array_equal(render(tile=best["tile"], group=best["group"], flags=best["flags"] | H.SPCONV_GRAPH),
                           base, equal_nan=True)
+
+
+def test_full_size_uneven_config_sampled(dev):
+    """The uneven workload at full size in the benchmark's launch form (one
+    persistent launch replayed from a HIP graph, tile 3072): 512 pink
+    sources of log-uniform length in [4096, 1048576], 1..8 directions x 2
+    ears of a 1,250-direction tap table, K = 16; sampled outputs of 64 rows
+    against the oracle's per-sample definition, with every row's first and
+    last samples."""
+    import torch
+    import paper_1502_03162_amd as H
+    n_src, F, K, lf, lg = 512, 2500, 16, 32, 169
+    lens = synth.uneven_lengths(300, n_src)
+    jobs = [(int(a), int(b)) for a, b in synth.jobs_uneven(300, n_src, F // 2)]
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(lf).astype(np.float32)
+    p, g = synth.random_taps(8, F, K, lg, nnz_min=12)
+    plan = H.Plan(r, p, g, lg)
+    srcs = [synth.pink(1000 + i, int(n)) for i, n in enumerate(lens)]
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    src = torch.from_numpy(np.concatenate(srcs)).to(dev)
+    out_off, total = H.row_layout(plan, lens, jobs)
+    out = torch.full((total,), float("nan"), dtype=torch.float32, device=dev)
+    b = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], tile=3072,
+                flags=H.SPCONV_PERSISTENT | H.SPCONV_GRAPH)
+    for _ in range(2):                                   # the graph is replayed
+        b.render(src, out)
+    torch.cuda.synchronize()
+    got, ref = [], []
+    for j in rng.choice(len(jobs), size=64, replace=False):
+        s, f = jobs[j]
+        L = plan.out_len(lens[s])
+        t = np.unique(np.concatenate([[0, 1, L - 1], rng.integers(0, L, 45)]))
+        got.append(out[torch.from_numpy(out_off[j] + t).to(dev)].cpu().numpy())
+        ref.append(oracle.sparse_render_points(r, srcs[s], p[f], g[f].astype(np.float64), t))
+    got, ref = np.concatenate(got), np.concatenate(ref)
+    assert np.all(np.isfinite(got))
+    assert oracle.rel_l2(got, ref) <= TOL
+    b.close()
+    plan.close()
+    del out, src
+    torch.cuda.empty_cache()
