@@ -519,7 +519,7 @@ def bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens, j
         return float(10 * np.log10(np.sum(10 ** (err[sel] / 10) * en) / np.sum(en)))
 
     t0 = time.perf_counter()
-    f1 = H.factorize(X, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False)
+    f1 = H.factorize(X, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False, device=True)
     lat = np.abs(np.repeat(np.sin(hs.az), 2))
     mid = float(np.median(lat[hs.contra]))
     reg = np.where(hs.contra, np.where(lat > mid, 2, 1), 0).astype(np.int32)
@@ -530,7 +530,8 @@ def bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens, j
     err = np.zeros(X.shape[0])
     for q in range(R):
         sel = reg == q
-        fq = H.factorize(X[sel], lf, 1000, args.k, g0=np.maximum(f1["G"][sel], 1e-12), lambda0=0.0, want_cost=False)
+        fq = H.factorize(X[sel], lf, 1000, args.k, g0=np.maximum(f1["G"][sel], 1e-12), lambda0=0.0, want_cost=False,
+                         device=True)
         rr[q] = fq["f"]
         p[sel], g[sel], err[sel] = fq["p"], fq["g"], fq["err_db"]
     fact_s = time.perf_counter() - t0
@@ -603,13 +604,23 @@ def main():
     n_src, ns, dps, lf, lg = 64, 1 << 20, 20, 32, 169
 
     log("HRIR set 1250 directions x 2 ears, factorizing")
-    t0 = time.perf_counter()
     hs = synth.hrir_set(0, 25, 50)
-    fac = H.factorize(hs.h, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False)
+    t0 = time.perf_counter()
+    fac = H.factorize(hs.h, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False, device=True)
+    t_dev = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fac_host = H.factorize(hs.h, lf, args.fact_iters, args.k, seed=7, lambda0=0.2, want_cost=False)
+    t_host = time.perf_counter() - t0
+    factorize_info = {"rows": int(hs.h.shape[0]), "taps": int(hs.h.shape[1]), "iters": args.fact_iters,
+                      "device_s": t_dev, "host_s": t_host, "host_threads": host_cpu()["affinity"],
+                      "max_abs_diff_f": float(np.max(np.abs(fac["f"] - fac_host["f"]))),
+                      "same_support": bool(np.array_equal(fac["p"], fac_host["p"]))}
+    del fac_host
     e_all = fac["err_db"]
     energy = np.sum(hs.h ** 2, axis=1)
     e_agg = float(10 * np.log10(np.sum(10 ** (e_all / 10) * energy) / np.sum(energy)))
-    log(f"factorized in {time.perf_counter() - t0:.1f} s: E_dB aggregate {e_agg:.2f}, worst {e_all.max():.2f}")
+    log(f"factorized on the GPU in {t_dev:.2f} s (host {t_host:.2f} s, same support "
+        f"{factorize_info['same_support']}): E_dB aggregate {e_agg:.2f}, worst {e_all.max():.2f}")
     r = fac["f"].astype(np.float32)
 
     log("sources: 64 pink x 1,048,576")
@@ -679,7 +690,7 @@ def main():
     k_sweep = {}
     for kk in [int(x) for x in args.k_sweep.split(",") if x]:
         t1 = time.perf_counter()
-        fk = H.factorize(hs.h, lf, args.fact_iters, kk, seed=7, lambda0=0.2, want_cost=False)
+        fk = H.factorize(hs.h, lf, args.fact_iters, kk, seed=7, lambda0=0.2, want_cost=False, device=True)
         ek = fk["err_db"]
         ek_agg = float(10 * np.log10(np.sum(10 ** (ek / 10) * np.sum(hs.h ** 2, axis=1)) / np.sum(hs.h ** 2)))
         pk = H.Plan(fk["f"].astype(np.float32), fk["p"], fk["g"], lg)
@@ -734,6 +745,7 @@ def main():
                      "algorithmic_bytes": alg_bytes,
                      "kernel": {"quad": "k_render_quad<32,16>", "register_window": "k_render_rw<32>",
                                 "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
+        "factorize": factorize_info,
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters, "sparsifiers": sparsifier},
         "legs": legs,

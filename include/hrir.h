@@ -45,7 +45,9 @@ const char* hrir_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Factorization: Toeplitz-constrained semi-NMF (Sec. III-C, Alg. 1),
- * followed by top-K sparsification.  Host only, FP64, synchronous.
+ * followed by top-K sparsification.  Host memory, FP64, synchronous; the
+ * iterations run on the host's cores, or on the GPU with
+ * HRIR_FACTORIZE_DEVICE.
  *
  * X            host f64[n][m]: the HRIR set, one HRIR per row.
  * lf           resonance length (the paper's M - K + 1, Eq. (13)); the
@@ -66,6 +68,11 @@ const char* hrir_last_error(void);
  * flags        HRIR_REFIT_NNLS: replace the kept gains by the non-negative
  *              least-squares fit of the HRIR on that support with f fixed
  *              (Eq. (14) with lambda = 0 on the support).
+ *              HRIR_FACTORIZE_DEVICE: run the iterations of Alg. 1 on the
+ *              current GPU (FP64, the host's arithmetic and order; lf <= 64
+ *              and m <= 4096, EINVAL otherwise); inputs and outputs stay in
+ *              host memory and the call still returns when everything is
+ *              done.
  * Outputs (host): f_out f64[lf] with ||f||_2 = 1; gdense_out f64[n][lg]
  * (optional) the dense G scaled to that f; p_out int32[n][k]; g_out
  * f32[n][k]; nnz_out int32[n] (optional) real taps per row; err_db_out
@@ -76,6 +83,7 @@ const char* hrir_last_error(void);
  * the resonance system is singular (e.g. G = 0); ENOMEM.
  * ---------------------------------------------------------------------- */
 #define HRIR_REFIT_NNLS 1u
+#define HRIR_FACTORIZE_DEVICE 2u
 
 int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf, int32_t iters,
                    uint64_t seed, const double* g0, double lambda0, int32_t k, uint32_t flags,

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_PKG, "libhrir.so")
 
 HRIR_OK, HRIR_EINVAL, HRIR_ENOMEM, HRIR_ENOTPD, HRIR_EAGAIN, HRIR_EDEVICE = 0, -1, -2, -3, -4, -5
 HRIR_REFIT_NNLS = 1
+HRIR_FACTORIZE_DEVICE = 2
 SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED, SPCONV_LDS_GATHER, SPCONV_REGWIN = 1, 2, 4, 8, 16
 
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOTPD", -4: "EAGAIN", -5: "EDEVICE"}
@@ -220,9 +221,10 @@ def _stream_handle(stream) -> int:
 # Factorization (host, FP64)
 # ---------------------------------------------------------------------------
 def factorize(X, lf: int, iters: int, k: int, seed: int = 0, g0=None, lambda0: float = 0.0,
-              refit: bool = True, want_cost: bool = True) -> dict:
+              refit: bool = True, want_cost: bool = True, device: bool = False) -> dict:
     """Toeplitz-constrained semi-NMF of an HRIR set X [n][m] (Alg. 1) and
-    top-k sparsification.  Returns f, G (dense), p, g, nnz, err_db, cost."""
+    top-k sparsification; device=True runs the iterations on the GPU.
+    Returns f, G (dense), p, g, nnz, err_db, cost."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     n, m = X.shape
     lg = max(m - lf + 1, 1)
@@ -236,7 +238,8 @@ def factorize(X, lf: int, iters: int, k: int, seed: int = 0, g0=None, lambda0: f
     g0a = None if g0 is None else np.ascontiguousarray(g0, dtype=np.float64)
     _check(_lib.hrir_factorize(_ptr(X, c_double), n, m, lf, iters, c_uint64(seed),
                                None if g0a is None else _ptr(g0a, c_double), lambda0, k,
-                               HRIR_REFIT_NNLS if refit else 0, _ptr(f, c_double), _ptr(G, c_double),
+                               (HRIR_REFIT_NNLS if refit else 0) | (HRIR_FACTORIZE_DEVICE if device else 0),
+                               _ptr(f, c_double), _ptr(G, c_double),
                                _ptr(p, c_int32), _ptr(g, c_float), _ptr(nnz, c_int32), _ptr(err, c_double),
                                None if cost is None else _ptr(cost, c_double)))
     return {"f": f, "G": G, "p": p, "g": g, "nnz": nnz, "err_db": err, "cost": cost}

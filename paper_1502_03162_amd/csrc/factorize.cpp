@@ -29,6 +29,9 @@ uint64_t splitmix_next(uint64_t& state) {
     return z ^ (z >> 31);
 }
 
+
+}  // namespace
+
 // L1 weight at iteration t of T: hold for 10%, geometric decay by 1e3 until
 // 50%, then zero.
 double l1_weight(double lambda0, int t, int T) {
@@ -37,8 +40,6 @@ double l1_weight(double lambda0, int t, int T) {
     if (t < stop) return lambda0 * std::pow(1000.0, -(t - hold) / (stop - hold));
     return 0.0;
 }
-
-}  // namespace
 
 // In-place Cholesky factorisation of an s x s SPD matrix (lower triangle)
 // followed by the two triangular solves for rhs.  Returns false if not PD.
@@ -244,7 +245,8 @@ extern "C" int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf,
     if (k < 1 || k > lg) return fail(HRIR_EINVAL, "hrir_factorize: need 1 <= k <= lg = %d (k=%d)", lg, k);
     if (!(lambda0 >= 0.0) || !std::isfinite(lambda0))
         return fail(HRIR_EINVAL, "hrir_factorize: lambda0 must be finite and >= 0");
-    if (flags & ~HRIR_REFIT_NNLS) return fail(HRIR_EINVAL, "hrir_factorize: unknown flags 0x%x", flags);
+    if (flags & ~(HRIR_REFIT_NNLS | HRIR_FACTORIZE_DEVICE))
+        return fail(HRIR_EINVAL, "hrir_factorize: unknown flags 0x%x", flags);
     for (int64_t i = 0; i < (int64_t)n * m; ++i)
         if (!std::isfinite(X[i])) return fail(HRIR_EINVAL, "hrir_factorize: X[%lld] is not finite", (long long)i);
 
@@ -268,7 +270,11 @@ extern "C" int hrir_factorize(const double* X, int32_t n, int32_t m, int32_t lf,
     }
 
     std::vector<double> rowe(n);
-    for (int t = 0; t < iters; ++t) {
+    if (flags & HRIR_FACTORIZE_DEVICE) {
+        const int rc = hrir::factorize_iterate_device(X, n, m, lf, iters, lambda0, G.data(), f.data(), cost_out);
+        if (rc) return rc;
+    }
+    for (int t = 0; t < iters && !(flags & HRIR_FACTORIZE_DEVICE); ++t) {
         int rc = hrir::resonance_step(pr, G.data(), f.data(), part);
         if (rc) return rc;
         double nrm = 0.0;

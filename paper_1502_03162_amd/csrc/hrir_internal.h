@@ -21,6 +21,14 @@ const char* last_error();
 // In-place Cholesky solve of the s x s SPD system H y = rhs (rhs overwritten
 // with y).  Returns false if H is not positive definite.
 bool spd_solve(std::vector<double>& H, int s, double* rhs);
+// L1 weight of the reflection update at iteration t of T (hrir_factorize).
+double l1_weight(double lambda0, int t, int T);
+// The iterations of Alg. 1 on the current GPU in FP64 (factorize_device.hip):
+// G (host, n x (m - lf + 1)) in and out, f (host, lf) out with unit norm,
+// cost (host, iters, or null) as in hrir_factorize.  Same arithmetic and order
+// as the host iterations.
+int factorize_iterate_device(const double* X, int n, int m, int lf, int iters, double lambda0, double* G,
+                             double* f, double* cost);
 
 // Lawson-Hanson active-set solution of min 1/2 y^T H y - c^T y over y >= 0,
 // H the s x s normal matrix.  Status code as in hrir.h.
