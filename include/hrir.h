@@ -345,7 +345,11 @@ void fftola_destroy(hrir_fft* plan);
  *     buffered) that the kernel reads in place -- no copy command precedes
  *     the launch -- so the call returns after enqueueing and jobs may be
  *     reused at once; a call waits only for the kernel of the call before
- *     the previous one (it reads the same half).
+ *     the previous one (it reads the same half).  Renders of one stream
+ *     object are ordered on the streams they are enqueued on: successive
+ *     calls that touch the same slot must use one HIP stream (or order
+ *     their streams), and calls on one object must not overlap in time
+ *     (one host thread at a time).
  * Errors: EINVAL (ranges, a stream twice in one call, buffers too small),
  * EDEVICE.
  * ---------------------------------------------------------------------- */
