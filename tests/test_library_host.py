@@ -188,3 +188,30 @@ def test_region_labels_are_validated_before_any_device_call():
         assert e.value.code == H.HRIR_EINVAL and "region" in str(e.value)
     with pytest.raises(H.HrirError):
         H.Plan(r, p, g, 9)                                  # two resonance filters need labels
+
+
+def test_product_code_never_uses_the_oracle():
+    """The oracle is test infrastructure: no source of the package (Python or
+    native) imports, loads or calls it."""
+    import pathlib
+    pkg = pathlib.Path(__file__).resolve().parents[1] / "paper_1502_03162_amd"
+    offenders = []
+    for f in pkg.rglob("*"):
+        if f.suffix not in (".py", ".hip", ".cpp", ".h") or "_build" in f.parts:
+            continue
+        text = f.read_text()
+        if "import oracle" in text or "from oracle" in text or "liboracle" in text or "or_sparse" in text:
+            offenders.append(str(f))
+    assert not offenders, offenders
+
+
+def test_bench_refuses_several_gpus():
+    import json
+    import pathlib
+    import subprocess
+    import sys
+    root = pathlib.Path(__file__).resolve().parents[1]
+    res = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                         timeout=120)
+    assert res.returncode != 0
+    assert "one GPU" in json.loads(res.stdout.strip().splitlines()[-1])["error"]
