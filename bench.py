@@ -649,6 +649,23 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"sparse K={args.k}: {ms:.3f} ms/step, {value:.4g} samples/s, {achieved:.0f} GB/s algorithmic")
 
+    # write references in the same output buffer: torch's fill of every
+    # row's samples (the bytes the render writes; a generic strided fill)
+    # and its zeroing of the whole buffer (a flat store stream); the render
+    # also reads its sources and computes, the fills only store
+    stride = int(out_off[1] - out_off[0]) if len(out_off) > 1 else plan.out_len(ns)
+    assert np.array_equal(out_off, np.arange(len(jobs), dtype=np.int64) * stride)
+    rows2d = out[:len(jobs) * stride].view(len(jobs), stride)[:, :plan.out_len(ns)]
+    fill_ms, _ = time_launches(lambda: rows2d.fill_(1.0), args.leg_steps, 1)
+    zero_ms, _ = time_launches(lambda: out.zero_(), args.leg_steps, 1)
+    write_ref = {"fill_rows_ms": fill_ms, "fill_rows_GBps": 4.0 * n_out / (fill_ms * 1e-3) / 1e9,
+                   "zero_buffer_ms": zero_ms, "zero_buffer_GBps": 4.0 * out.numel() / (zero_ms * 1e-3) / 1e9,
+                 "render_ms_over_fill_rows_ms": ms / fill_ms, "render_ms_over_zero_buffer_ms": ms / zero_ms,
+                 "note": "torch's strided fill of the render's output rows (same bytes) and its zeroing of the "
+                         "whole buffer (flat store stream)"}
+    log(f"write references: torch fill of the output rows {fill_ms:.3f} ms ({write_ref['fill_rows_GBps']:.0f} GB/s), "
+        f"zero of the whole buffer {zero_ms:.3f} ms ({write_ref['zero_buffer_GBps']:.0f} GB/s)")
+
     # comparison legs on the same GPU, same sources and rows (a dense row has
     # the same length: 200-tap HRIR, src_len + 199)
     legs = {}
@@ -745,6 +762,7 @@ def main():
                      "algorithmic_bytes": alg_bytes,
                      "kernel": {"quad": "k_render_quad<32,16>", "register_window": "k_render_rw<32>",
                                 "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
+        "write_reference": write_ref,
         "factorize": factorize_info,
         "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
                     "fact_iters": args.fact_iters, "sparsifiers": sparsifier},
