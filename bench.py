@@ -469,12 +469,13 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
     srcs = np.concatenate([synth.pink(900 + i, N) for i in range(n_src)])
     src = torch.from_numpy(srcs).to(dev)
     by_tile = {}
-    for tile in (1024, 2048, 4096):
+    tiles = (1536, 2048, 2560, 3072)
+    for tile in tiles:
         mv = H.Moving(plan, n_src, N, seg, fade, tile)
         stride = (mv.out_len + 63) // 64 * 64
         out = torch.empty(2 * n_src * stride, device=dev)
         by_tile[tile], _ = time_launches(lambda: mv.render(src, seg_filt, out, stride), args.steps, args.warmup)
-        if tile != 4096:
+        if tile != tiles[-1]:
             mv.close()
     best_tile = min(by_tile, key=by_tile.get)
     mms = by_tile[best_tile]

@@ -480,7 +480,7 @@ void stream_close(hrir_server* server);
  *                   t - j seg_len < fade with j >= 1, the output is
  *                   a y_j + (1 - a) y_{j-1}, a = (u + 1) / fade, y_j the render
  *                   with segment j's filter.  tile: outputs per workgroup, a
- *                   multiple of 256 up to 4096 (0: 2048).  The plan must
+ *                   multiple of 256 up to 4096 (0: 2560).  The plan must
  *                   outlive the object.
  * moving_render     seg_filt host i32[n_src][n_seg][2] plan rows (left,
  *                   right) per segment, validated and staged through pinned

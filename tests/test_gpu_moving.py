@@ -148,10 +148,10 @@ def test_moving_tile_lengths_agree_bitwise(dev):
 
 
 def test_full_size_moving_config(dev):
-    """The moving-source workload at full size in the benchmark's launch
-    shape: 128 pink sources of 262,144 samples, a direction every 512
-    samples with a 64-sample crossfade, K = 16, tile 2048; 6 sources (both
-    ears, every sample) against the oracle."""
+    """The moving-source workload at full size: 128 pink sources of 262,144
+    samples, a direction every 512 samples with a 64-sample crossfade,
+    K = 16, the default tile (2560; the benchmark sweeps 1536..3072); 6
+    sources (both ears, every sample) against the oracle."""
     import torch
     h = H()
     n_src, n, seg, fade, lf, lg, k, F = 128, 262144, 512, 64, 32, 169, 16, 2500
@@ -159,7 +159,7 @@ def test_full_size_moving_config(dev):
     r = rng.standard_normal(lf).astype(np.float32)
     p, g = synth.random_taps(12, F, k, lg, nnz_min=8)
     plan = h.Plan(r, p, g, lg)
-    mv = h.Moving(plan, n_src, n, seg, fade, 2048)
+    mv = h.Moving(plan, n_src, n, seg, fade)
     seg_filt = rng.integers(0, F, (n_src, mv.n_seg, 2)).astype(np.int32)
     srcs = np.stack([synth.pink(900 + i, n) for i in range(n_src)])
     stride = (mv.out_len + 63) // 64 * 64
