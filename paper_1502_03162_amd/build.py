@@ -76,5 +76,14 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def assemble(src: str, out_path: str) -> str:
+    """gfx950 device assembly of one HIP source, with the library's flags
+    (for inspection of the generated code)."""
+    cmd = [hipcc(), *HIPCC_FLAGS, *EXTRA.get(src, []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "--cuda-device-only", "-S", "-o", out_path, os.path.join(CSRC, src)]
+    _run(cmd, False)
+    return out_path
+
+
 if __name__ == "__main__":
     print(build(verbose="-q" not in sys.argv))
