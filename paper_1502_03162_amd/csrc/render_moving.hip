@@ -11,9 +11,13 @@
 // predicted filter never leaves the GPU.
 //
 // Kernel: the quad tile of render_quad.h (one source, TB outputs, z as four
-// shifted LDS copies) and work items of 256 outputs x one ear (one quad per
-// lane); seg_len is a multiple of 256, so an item lies inside one segment and
-// only an item that starts a segment blends.
+// shifted LDS copies) and work items of NJ x 256 outputs x one ear (NJ quads
+// per lane, 256 outputs apart); seg_len and TB are multiples of NJ x 256, so
+// an item lies inside one segment and only an item that starts a segment
+// blends, over its first quad (fade <= 256).  Taps are staged in LDS as
+// offsets into the quad copies (c CS + H - p - c for position p, c = (H - p)
+// mod 4) with their gains, read 4 at a time, so a tap costs one address add
+// and NJ 16-byte z reads for 4 NJ fmas.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,48 +36,64 @@ constexpr int kMovItem = 256;     // outputs per work item (one quad per lane)
 // Filters a tile can need: both ears of every segment it overlaps and of the
 // segment before (its last samples fade into the tile's first segment).
 __host__ __device__ inline int moving_tile_filters(int TB) { return 2 * (TB / kMovItem + 2); }
+// The filter-row slots, rounded up so the tap arrays after them are 16-byte aligned.
+__host__ __device__ inline int moving_row_slots(int TB) { return (moving_tile_filters(TB) + 3) / 4 * 4; }
 
-// LDS floats after the z copies: filter rows, then their positions and gains.
+// LDS floats after the z copies: filter rows, then their tap offsets and gains.
 template <int KP>
-__host__ __device__ inline int moving_tap_lds(int TB) { return moving_tile_filters(TB) * (1 + 2 * KP); }
-
-// Empty asm over the 4 accumulators that clobbers memory: LDS reads of the
-// next group of taps are not hoisted above it (all of them in flight at once
-// would take 4 VGPRs per tap and cost occupancy).  Emits no instruction.
-__device__ __forceinline__ void pin4(float (&a)[4]) {
-    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]) : : "memory");
+__host__ __device__ inline int moving_tap_lds(int TB) {
+    return moving_row_slots(TB) + 2 * KP * moving_tile_filters(TB);
 }
 
-// pp, gg: one filter's taps staged in LDS (every lane reads the same words).
-// Taps in groups of 4 (KP is a multiple of 4), accumulated in tap order.
-template <int KP>
-__device__ __forceinline__ void quad_taps(const float* zl, int CS, int H, const int* pp, const float* gg,
-                                          float (&acc)[4]) {
+// Empty asm over the accumulators that clobbers memory: LDS reads of the
+// next group of taps are not hoisted above it (all of them in flight at once
+// would take 4 VGPRs per tap and read and cost occupancy).  Emits no
+// instruction.
+template <int NJ>
+__device__ __forceinline__ void pin_acc(float (&a)[NJ][4]) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj)
+        asm volatile("" : "+v"(a[jj][0]), "+v"(a[jj][1]), "+v"(a[jj][2]), "+v"(a[jj][3]) : : "memory");
+}
+
+// offs, gs: one filter's staged taps (LDS offsets into the quad copies and
+// gains; 16-byte aligned, every lane reads the same words).  Taps in groups
+// of 4 (KP is a multiple of 4), accumulated in tap order; the first NJ of
+// the item's quads, 256 outputs apart.
+template <int KP, int NJ, int NA>
+__device__ __forceinline__ void quad_taps(const float* zl, const int* offs, const float* gs, float (&acc)[NA][4]) {
     static_assert(KP % 4 == 0, "taps come in groups of 4");
+    static_assert(NJ <= NA, "accumulators for every quad");
 #pragma unroll
     for (int q0 = 0; q0 < KP; q0 += 4) {
-        float4 v[4];
-        float g[4];
+        const int4 o4 = *reinterpret_cast<const int4*>(offs + q0);
+        const float4 g4 = *reinterpret_cast<const float4*>(gs + q0);
+        // the same words for every lane: keep the taps in scalar registers
+        const int o[4] = {__builtin_amdgcn_readfirstlane(o4.x), __builtin_amdgcn_readfirstlane(o4.y),
+                          __builtin_amdgcn_readfirstlane(o4.z), __builtin_amdgcn_readfirstlane(o4.w)};
+        const float g[4] = {__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.x))),
+                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.y))),
+                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.z))),
+                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.w)))};
+        float4 v[4][NJ];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            // the same word for every lane: keep the tap in scalar registers
-            const int p = __builtin_amdgcn_readfirstlane(pp[q0 + u]);
-            g[u] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(gg[q0 + u])));
-            const int c = (H - p) & 3;
-            v[u] = *reinterpret_cast<const float4*>(zl + c * CS + (H - p - c));
-        }
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            acc[0] = fmaf(g[u], v[u].x, acc[0]);
-            acc[1] = fmaf(g[u], v[u].y, acc[1]);
-            acc[2] = fmaf(g[u], v[u].z, acc[2]);
-            acc[3] = fmaf(g[u], v[u].w, acc[3]);
-        }
-        pin4(acc);
+            for (int jj = 0; jj < NJ; ++jj) v[u][jj] = *reinterpret_cast<const float4*>(zl + o[u] + 256 * jj);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                acc[jj][0] = fmaf(g[u], v[u][jj].x, acc[jj][0]);
+                acc[jj][1] = fmaf(g[u], v[u][jj].y, acc[jj][1]);
+                acc[jj][2] = fmaf(g[u], v[u][jj].z, acc[jj][2]);
+                acc[jj][3] = fmaf(g[u], v[u][jj].w, acc[jj][3]);
+            }
+        pin_acc<NA>(acc);
     }
 }
 
-template <int LFP, int KP>
+template <int LFP, int KP, int NJ>
 __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __restrict__ src,
                                                                 const TileDesc* __restrict__ tiles,
                                                                 const int32_t* __restrict__ seg_filt, int n_seg,
@@ -82,12 +102,14 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
                                                                 const float* __restrict__ Gv,
                                                                 float* __restrict__ out, int64_t out_stride, int lg,
                                                                 int TB) {
+    constexpr int IL = NJ * kMovItem;                            // outputs per work item
     extern __shared__ float4 smem4[];
     float* lds = reinterpret_cast<float*>(smem4);
     const TileDesc td = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int s = td.job_begin;                                  // source index
     const int tile_len = min(TB, td.out_len - td.t0);
+    const int H = lg - 1, CS = quad_cs(TB, H);
     // The tile's filters: segments j_lo .. j_hi, both ears.  Their rows are
     // read before the source is staged and their taps copied into LDS while
     // the source window is ready, so no work item waits on a chain of
@@ -100,49 +122,59 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
     int f_mine = 0;
     if (tid < n_fl) f_mine = seg_filt[(row + j_lo) * 2 + tid];
     int* lds_f = reinterpret_cast<int*>(lds + lds_quad_len(TB, lg, LFP));
-    int* lds_p = lds_f + moving_tile_filters(TB);
-    float* lds_g = reinterpret_cast<float*>(lds_p + moving_tile_filters(TB) * KP);
+    int* lds_o = lds_f + moving_row_slots(TB);
+    float* lds_g = reinterpret_cast<float*>(lds_o + moving_tile_filters(TB) * KP);
     quad_stage<LFP>(td, src, r, lg, TB, lds, tid, [&]() {
         if (tid < n_fl) lds_f[tid] = f_mine;
         __syncthreads();
         for (int a = tid; a < n_fl * KP; a += kQThreads) {
             const int64_t o = (int64_t)lds_f[a / KP] * KP + a % KP;
-            lds_p[a] = P[o];
+            const int p = P[o];
+            const int c = (H - p) & 3;
+            lds_o[a] = c * CS + (H - p - c);
             lds_g[a] = Gv[o];
         }
     });
-    const int H = lg - 1, CS = quad_cs(TB, H);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int n_items = 2 * ((tile_len + kMovItem - 1) / kMovItem);
+    const int n_items = 2 * ((tile_len + IL - 1) / IL);
     for (int it = wave; it < n_items; it += kQWaves) {
         const int e = it & 1, blk = it >> 1;
-        const int t_blk = td.t0 + kMovItem * blk;
+        const int t_blk = td.t0 + IL * blk;
         const int j_raw = t_blk / seg_len;
         const int j = min(j_raw, n_seg - 1);
         const int fi = 2 * (j - j_lo) + e;
-        const float* zl = lds + kMovItem * blk + 4 * lane;
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        quad_taps<KP>(zl, CS, H, lds_p + fi * KP, lds_g + fi * KP, acc);
+        const float* zl = lds + IL * blk + 4 * lane;
+        float acc[NJ][4];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = acc[jj][3] = 0.0f;
+        quad_taps<KP, NJ>(zl, lds_o + fi * KP, lds_g + fi * KP, acc);
         if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len) {
-            float acc0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            quad_taps<KP>(zl, CS, H, lds_p + (fi - 2) * KP, lds_g + (fi - 2) * KP, acc0);
+            // the previous segment's filter over the first quad (fade <= 256)
+            float acc0[1][4] = {{0.0f, 0.0f, 0.0f, 0.0f}};
+            quad_taps<KP, 1>(zl, lds_o + (fi - 2) * KP, lds_g + (fi - 2) * KP, acc0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 4 * lane + i;
                 if (u < fade) {
+                    // one rounding order in every instantiation: (1 - a) y0, then fma
                     const float a = (float)(u + 1) / (float)fade;
-                    acc[i] = a * acc[i] + (1.0f - a) * acc0[i];
+                    const float b = (1.0f - a) * acc0[0][i];
+                    acc[0][i] = fmaf(a, acc[0][i], b);
                 }
             }
         }
-        float* orow = out + ((int64_t)s * 2 + e) * out_stride + t_blk;
-        const int lim = tile_len - kMovItem * blk;
-        if (lim >= kMovItem && ((reinterpret_cast<uintptr_t>(orow) & 15) == 0)) {
-            *reinterpret_cast<float4*>(orow + 4 * lane) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (4 * lane + i < lim) orow[4 * lane + i] = acc[i];
+        for (int jj = 0; jj < NJ; ++jj) {
+            float* orow = out + ((int64_t)s * 2 + e) * out_stride + t_blk + kMovItem * jj;
+            const int lim = tile_len - IL * blk - kMovItem * jj;
+            if (lim >= kMovItem && ((reinterpret_cast<uintptr_t>(orow) & 15) == 0)) {
+                *reinterpret_cast<float4*>(orow + 4 * lane) =
+                    make_float4(acc[jj][0], acc[jj][1], acc[jj][2], acc[jj][3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4 * lane + i < lim) orow[4 * lane + i] = acc[jj][i];
+            }
         }
     }
 }
@@ -246,6 +278,7 @@ extern "C" int spconv_plan_topk(hrir_plan* plan, int32_t first_row, const float*
 struct hrir_moving {
     const hrir_plan* plan = nullptr;
     int n_src = 0, n_seg = 0, seg_len = 0, fade = 0, TB = 2048;
+    int nj = 1;                                   // quads per lane and work item
     int64_t src_len = 0, out_len = 0;
     int64_t n_tiles = 0;
     size_t lds = 0;
@@ -306,6 +339,7 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     m->seg_len = seg_len;
     m->fade = fade;
     m->TB = tile;
+    m->nj = (seg_len % (2 * kMovItem) == 0 && tile % (2 * kMovItem) == 0) ? 2 : 1;
     m->n_seg = (int)((src_len + seg_len - 1) / seg_len);
     m->out_len = src_len + pv.lf + pv.lg - 2;
     const int rc_lds = with_lf_k(pv.lfp, pv.kp, [&](auto, auto K) -> int {
@@ -333,9 +367,10 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     }
     if (e == hipSuccess) {
         const int rc = with_lf_k(pv.lfp, pv.kp, [&](auto L, auto K) -> int {
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(
-                                        &k_render_moving<decltype(L)::value, decltype(K)::value>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds);
+            constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+            const void* k = m->nj == 2 ? reinterpret_cast<const void*>(&k_render_moving<LV, KV, 2>)
+                                       : reinterpret_cast<const void*>(&k_render_moving<LV, KV, 1>);
+            e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds);
             return HRIR_OK;
         });
         if (rc) {
@@ -379,9 +414,15 @@ extern "C" int moving_render(hrir_moving* m, const float* d_src, int64_t src_ele
     if (e == hipSuccess) e = hipEventRecord(m->used[b], st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "moving_render: %s", hipGetErrorString(e));
     int rc = with_lf_k(pv.lfp, pv.kp, [&](auto L, auto K) -> int {
-        hipLaunchKernelGGL((k_render_moving<decltype(L)::value, decltype(K)::value>), dim3((unsigned)m->n_tiles),
-                           dim3(kQThreads), m->lds, st, d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade,
-                           pv.d_r, pv.d_p, pv.d_g, d_out, out_stride, pv.lg, m->TB);
+        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        if (m->nj == 2)
+            hipLaunchKernelGGL((k_render_moving<LV, KV, 2>), dim3((unsigned)m->n_tiles), dim3(kQThreads), m->lds, st,
+                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, pv.d_p, pv.d_g,
+                               d_out, out_stride, pv.lg, m->TB);
+        else
+            hipLaunchKernelGGL((k_render_moving<LV, KV, 1>), dim3((unsigned)m->n_tiles), dim3(kQThreads), m->lds, st,
+                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, pv.d_p, pv.d_g,
+                               d_out, out_stride, pv.lg, m->TB);
         return HRIR_OK;
     });
     if (rc) return rc;

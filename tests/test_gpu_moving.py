@@ -68,7 +68,7 @@ def _moving_case(seed, n_src, n, lf, lg, k, F):
 
 @pytest.mark.parametrize("n,seg,fade,lf,lg,k", [(20000, 512, 64, 32, 169, 16), (20000, 256, 0, 32, 169, 16),
                                                  (9000, 256, 256, 5, 40, 3), (5000, 768, 100, 64, 2048, 64),
-                                                 (100, 256, 64, 32, 169, 16)])
+                                                 (100, 256, 64, 32, 169, 16), (12000, 1024, 256, 16, 100, 8)])
 def test_moving_render_matches_oracle(dev, n, seg, fade, lf, lg, k):
     import torch
     h = H()
