@@ -469,7 +469,7 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
     srcs = np.concatenate([synth.pink(900 + i, N) for i in range(n_src)])
     src = torch.from_numpy(srcs).to(dev)
     by_tile = {}
-    tiles = (1536, 2048, 2560, 3072)
+    tiles = (2048, 2560, 3072, 4096)
     for tile in tiles:
         mv = H.Moving(plan, n_src, N, seg, fade, tile)
         stride = (mv.out_len + 63) // 64 * 64

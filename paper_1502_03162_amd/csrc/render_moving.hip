@@ -327,7 +327,7 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     if (seg_len < kMovItem || seg_len % kMovItem)
         return fail(HRIR_EINVAL, "moving_create: seg_len=%d must be a positive multiple of %d", seg_len, kMovItem);
     if (fade < 0 || fade > kMovItem) return fail(HRIR_EINVAL, "moving_create: fade=%d outside [0, %d]", fade, kMovItem);
-    if (tile == 0) tile = 2560;     // measured best of 1536..3072 for 2 rows per source
+    if (tile == 0) tile = 2560;     // 2048..4096 measured within 5 % for 2 rows per source
     if (tile < kMovItem || tile % kMovItem || tile > kQuadTileMax)
         return fail(HRIR_EINVAL, "moving_create: tile=%d must be a multiple of %d in [%d, %d]", tile, kMovItem,
                     kMovItem, kQuadTileMax);

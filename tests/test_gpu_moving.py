@@ -150,7 +150,7 @@ def test_moving_tile_lengths_agree_bitwise(dev):
 def test_full_size_moving_config(dev):
     """The moving-source workload at full size: 128 pink sources of 262,144
     samples, a direction every 512 samples with a 64-sample crossfade,
-    K = 16, the default tile (2560; the benchmark sweeps 1536..3072); 6
+    K = 16, the default tile (2560; the benchmark sweeps 2048..4096); 6
     sources (both ears, every sample) against the oracle."""
     import torch
     h = H()
