@@ -749,6 +749,11 @@ def main():
         "ms_median": float(np.median(per)),
         "ms_min": float(np.min(per)),
         "higher_is_better": True,
+        "timing": {"method": f"HIP events on the launch stream around {args.steps} launches after "
+                             f"{args.warmup} warm-ups; ms_per_step is their mean, ms_median and ms_min per launch",
+                   "excluded": ["device allocation", "plan and batch creation (tap tables, tile descriptors)",
+                                "host-to-device copy of the sources (inputs resident in HBM)",
+                                "the factorization", "FFT overlap-add filter spectra (precomputed)"]},
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
