@@ -493,7 +493,7 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
            "fallback_fraction": float(np.mean(choice >= 0)),
            "inference": {"queries": nq, "ms": inf_ms, "queries_per_s": nq / (inf_ms * 1e-3)},
            "moving_render": {"ms_per_step": mms, "output_samples_per_s": n_out / (mms * 1e-3),
-                             "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "kernel": "k_render_moving<32,16>",
+                             "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "kernel": "k_render_moving<32,16,2>",
                              "tile": best_tile, "ms_by_tile": {str(k): v for k, v in by_tile.items()}}}
     log(f"surrogate inference: {nq} directions in {inf_ms:.3f} ms; fallback {100 * np.mean(choice >= 0):.1f} %; "
         f"moving render {mms:.3f} ms, {n_out / (mms * 1e-3):.3g} samples/s")
