@@ -66,16 +66,21 @@ def _moving_case(seed, n_src, n, lf, lg, k, F):
     return r, p, g, srcs, rng
 
 
-@pytest.mark.parametrize("n,seg,fade,lf,lg,k", [(20000, 512, 64, 32, 169, 16), (20000, 256, 0, 32, 169, 16),
-                                                 (9000, 256, 256, 5, 40, 3), (5000, 768, 100, 64, 2048, 64),
-                                                 (100, 256, 64, 32, 169, 16), (12000, 1024, 256, 16, 100, 8)])
-def test_moving_render_matches_oracle(dev, n, seg, fade, lf, lg, k):
+@pytest.mark.parametrize("n,seg,fade,lf,lg,k,tile", [(20000, 512, 64, 32, 169, 16, 0), (20000, 256, 0, 32, 169, 16, 0),
+                                                      (9000, 256, 256, 5, 40, 3, 0), (5000, 768, 100, 64, 2048, 64, 0),
+                                                      (100, 256, 64, 32, 169, 16, 0), (12000, 1024, 256, 16, 100, 8, 0),
+                                                      (9000, 512, 256, 64, 2048, 64, 4096),
+                                                      (20000, 512, 64, 32, 169, 16, 1536)])
+def test_moving_render_matches_oracle(dev, n, seg, fade, lf, lg, k, tile):
+    """Moving sources against the oracle; the last two cases: the largest
+    tile with the longest filter (LDS near its limit), and a 512-output-item
+    tile that is not a power of two."""
     import torch
     h = H()
     n_src, F = 3, 12
     r, p, g, srcs, rng = _moving_case(n + seg + fade, n_src, n, lf, lg, k, F)
     plan = h.Plan(r, p, g, lg)
-    mv = h.Moving(plan, n_src, n, seg, fade)
+    mv = h.Moving(plan, n_src, n, seg, fade, tile)
     n_seg = (n + seg - 1) // seg
     assert mv.n_seg == n_seg and mv.out_len == n + lf + lg - 2
     seg_filt = rng.integers(0, F, (n_src, n_seg, 2)).astype(np.int32)

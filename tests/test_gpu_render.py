@@ -101,6 +101,29 @@ def test_ragged_lengths_and_shapes(dev, lf, lg, k, kernel):
     check(rows, oracle_rows(r, srcs, p, g, lg, jobs))
 
 
+def test_largest_tile_and_longest_filter(dev):
+    """The default kernel at its limits: tile 4096 (the largest), lg = 2048
+    (the longest reflection filter a plan takes), K = 64 and lf = 64, so one
+    tile's z window spans 6,143 samples in four LDS copies (98 KB); plain
+    and persistent launches against the oracle, and bitwise against each
+    other and the default tile."""
+    h = H()
+    rng = np.random.default_rng(2048)
+    lf, lg, k, F = 64, 2048, 64, 5
+    r = rng.standard_normal(lf).astype(np.float32)
+    p, g = synth.random_taps(77, F, k, lg, nnz_min=k)
+    p[0, 0], p[1, k - 1] = 0, lg - 1
+    srcs = [synth.white(300 + i, n) for i, n in enumerate([1, 4095, 4097, 12289])]
+    jobs = [(i, (2 * i + j) % F) for i in range(len(srcs)) for j in range(3)]
+    plan = h.Plan(r, p, g, lg)
+    base = render_rows(plan, srcs, jobs, dev, tile=4096)
+    check(base, oracle_rows(r, srcs, p, g, lg, jobs))
+    for v in (dict(tile=4096, flags=h.SPCONV_PERSISTENT, reps=2), dict(), dict(tile=1024)):
+        rows = render_rows(plan, srcs, jobs, dev, **v)
+        for a, b in zip(rows, base):
+            assert np.array_equal(a, b), v
+
+
 def _variant_setup(seed=0):
     h = H()
     rng = np.random.default_rng(seed)
