@@ -148,8 +148,11 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = acc[jj][3] = 0.0f;
         quad_taps<KP, NJ>(zl, lds_o + fi * KP, lds_g + fi * KP, acc);
-        if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len) {
-            // the previous segment's filter over the first quad (fade <= 256)
+        if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len && 4 * lane < fade) {
+            // the previous segment's filter over the first quad (fade <= 256),
+            // in the lanes whose outputs blend (the others skip its LDS reads;
+            // the taps are the same words for every lane, so any active lane
+            // gives them to readfirstlane)
             float acc0[1][4] = {{0.0f, 0.0f, 0.0f, 0.0f}};
             quad_taps<KP, 1>(zl, lds_o + (fi - 2) * KP, lds_g + (fi - 2) * KP, acc0);
 #pragma unroll
