@@ -203,7 +203,7 @@ typedef struct {
  *              src_len >= 1.
  * jobs         host spconv_job[n_jobs]; n_jobs may be 0 (render is a no-op).
  * tile         outputs per work tile: a multiple of 1024 up to 4096 for the
- *              default kernel (default 3072), of 1024 up to 16384 for
+ *              default kernel (default 2048), of 1024 up to 16384 for
  *              LDS_GATHER (default 4096), of 6144 up to 16384 for REGWIN
  *              (default 6144).
  * group        max jobs sharing one staged z tile (0 = all jobs of a source).

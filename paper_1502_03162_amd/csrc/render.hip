@@ -459,8 +459,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
                                                    : KIND_QUAD;
     const int tile_unit = kind == KIND_REGWIN ? kTileRW : kChunk;
     const int tile_max = kind == KIND_QUAD ? kQuadTileMax : 16384;
-    // default quad tile 3072 (3 tiles per CU): 1-3 % ahead of 2048 (4 per CU) on 20 directions x 2 ears
-    if (tile == 0) tile = kind == KIND_REGWIN ? kTileRW : kind == KIND_QUAD ? 3072 : 4096;
+    if (tile == 0) tile = kind == KIND_REGWIN ? kTileRW : kind == KIND_QUAD ? 2048 : 4096;
     if (tile < tile_unit || tile % tile_unit || tile > tile_max)
         return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, %d]", tile,
                     tile_unit, tile_unit, tile_max);

@@ -45,10 +45,13 @@ struct NoHook {
 // tid: this thread's index in the workgroup (a persistent caller passes one
 // the compiler cannot see as loop-invariant, so that nothing derived from
 // it is hoisted out of its loop over tiles).
+// prio (wave-uniform): raise the waves' issue priority while the source
+// window is loaded, so a new tile's loads go out ahead of other tiles'
+// gathers on the CU; it pays when the gather is long (many jobs per tile).
 template <int LFP, class Hook = NoHook>
 __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __restrict__ src,
                                            const float* __restrict__ r, int lg, int TB, float* lds, int tid,
-                                           Hook&& after_source = Hook{}) {
+                                           Hook&& after_source = Hook{}, bool prio = false) {
     const int H = lg - 1;
     const int tile_len = min(TB, td.out_len - td.t0);
     const int NZ = tile_len + H + 3;           // z_win[u], u < NZ, covers every quad read
@@ -57,8 +60,10 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
     float* s_win = lds;
     float* zc = lds;                           // the copies overwrite s_win after the FIR
 
+    if (prio) __builtin_amdgcn_s_setprio(2);
     stage_s<LFP, kQThreads>(td, src, H, nz8, s_win, tid);
     after_source();
+    if (prio) __builtin_amdgcn_s_setprio(0);
 
     // FIR into registers: zz[ps][a] = z_win[u0 + a], u0 = 8 (256 ps + tid)
     float rr[LFP];
@@ -109,7 +114,6 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
         }
     }
     __syncthreads();
-
 }
 
 }  // namespace hrir

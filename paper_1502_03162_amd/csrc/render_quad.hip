@@ -32,12 +32,16 @@
 
 namespace hrir {
 
+// Tiles with at least this many jobs stage their source at raised wave
+// priority (measured: 2-3 % faster at 40 jobs per tile, slower at 1..16).
+constexpr int kQPrioJobs = 24;
+
 template <int LFP, int KP>
 __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float* __restrict__ src,
                                                  const JobDesc* __restrict__ jobs, const float* __restrict__ r,
                                                  const int* __restrict__ P, const float* __restrict__ Gv,
                                                  float* __restrict__ out, int lg, int TB, float* lds, int tid) {
-    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid);
+    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid, NoHook{}, td.job_count >= kQPrioJobs);
     const int H = lg - 1;
     const int CS = quad_cs(TB, H);
     const float* zc = lds;
