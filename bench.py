@@ -670,13 +670,24 @@ def main():
     rows2d = out[:len(jobs) * stride].view(len(jobs), stride)[:, :plan.out_len(ns)]
     fill_ms, _ = time_launches(lambda: rows2d.fill_(1.0), args.leg_steps, 1)
     zero_ms, _ = time_launches(lambda: out.zero_(), args.leg_steps, 1)
+    # a device-to-device copy between the buffer's two halves: the measured
+    # streaming rate (bytes read + bytes written) the render is compared with
+    half = (out.numel() // 2) // 1024 * 1024
+    lo, hi = out[:half], out[half:2 * half]
+    copy_ms, _ = time_launches(lambda: hi.copy_(lo), args.leg_steps, 1)
+    copy_gbs = 8.0 * half / (copy_ms * 1e-3) / 1e9
     write_ref = {"fill_rows_ms": fill_ms, "fill_rows_GBps": 4.0 * n_out / (fill_ms * 1e-3) / 1e9,
                    "zero_buffer_ms": zero_ms, "zero_buffer_GBps": 4.0 * out.numel() / (zero_ms * 1e-3) / 1e9,
                  "render_ms_over_fill_rows_ms": ms / fill_ms, "render_ms_over_zero_buffer_ms": ms / zero_ms,
-                 "note": "torch's strided fill of the render's output rows (same bytes) and its zeroing of the "
-                         "whole buffer (flat store stream)"}
+                 "d2d_copy_bytes": 8.0 * half, "d2d_copy_ms": copy_ms, "d2d_copy_GBps": copy_gbs,
+                 "render_frac_of_d2d_copy": achieved / copy_gbs,
+                 "note": "torch's strided fill of the render's output rows (same bytes), its zeroing of the "
+                         "whole buffer (flat store stream), and a device copy between the buffer's halves "
+                         "(GB/s counts bytes read plus bytes written)"}
     log(f"write references: torch fill of the output rows {fill_ms:.3f} ms ({write_ref['fill_rows_GBps']:.0f} GB/s), "
-        f"zero of the whole buffer {zero_ms:.3f} ms ({write_ref['zero_buffer_GBps']:.0f} GB/s)")
+        f"zero of the whole buffer {zero_ms:.3f} ms ({write_ref['zero_buffer_GBps']:.0f} GB/s), "
+        f"copy of {8.0 * half / 1e9:.2f} GB {copy_ms:.3f} ms ({copy_gbs:.0f} GB/s; the render reaches "
+        f"{achieved / copy_gbs:.1%} of it)")
 
     # comparison legs on the same GPU, same sources and rows (a dense row has
     # the same length: 200-tap HRIR, src_len + 199)
