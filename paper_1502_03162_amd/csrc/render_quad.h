@@ -18,6 +18,7 @@ constexpr int kQWaves = kQThreads / 64;
 constexpr int kQPass = 2;             // FIR passes of 8 z values per thread (8192 z: tiles up to 4096)
 static_assert(kQChunk == 1024, "quad chunk");
 static_assert(kQPass * kQThreads * kZpt >= kQuadTileMax + 2048 + 3, "FIR passes cover the largest tile");
+static_assert(kZpt == 8, "the copy stores rotate 8 values per lane by lane / 8");
 
 // Floats per shifted copy: holds m < TB + H (+ padding so that the copies
 // start on different banks).
@@ -99,10 +100,29 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
             float* z0 = zc + u0;
             *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);
             *reinterpret_cast<float4*>(z0 + 4) = make_float4(zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]);
+            // Copies 1..3 are not 16-byte aligned: one dword per lane per
+            // store.  Lanes are 8 dwords apart, so if every lane stored the
+            // same element a, 8 lanes would share each bank.  Store k writes
+            // element (k + lane / 8) mod 8 instead, which puts the 64 lanes
+            // on 64 different banks; the lane's values are rotated by
+            // lane / 8 to match (a three-stage barrel shift).
+            const int g = (tid >> 3) & 7;
+            float zr[kZpt];
+#pragma unroll
+            for (int a = 0; a < kZpt; ++a) zr[a] = zz[ps][a];
+#pragma unroll
+            for (int b = 1; b < kZpt; b <<= 1) {
+                float t[kZpt];
+#pragma unroll
+                for (int k = 0; k < kZpt; ++k) t[k] = (g & b) ? zr[(k + b) & (kZpt - 1)] : zr[k];
+#pragma unroll
+                for (int k = 0; k < kZpt; ++k) zr[k] = t[k];
+            }
+            // zr[k] = zz[ps][(k + g) mod 8]
 #pragma unroll
             for (int c = 1; c < 4; ++c)
 #pragma unroll
-                for (int a = 0; a < kZpt; ++a) zc[c * CS + u0 + a - c] = zz[ps][a];
+                for (int k = 0; k < kZpt; ++k) zc[c * CS + u0 + ((k + g) & (kZpt - 1)) - c] = zr[k];
         } else if (u0 < nz8) {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
