@@ -130,9 +130,8 @@ def cpu_baseline(r, srcs, p, g, lg, jobs, n_src_sample: int, chunk: int = 4, rep
     secs = ", ".join(f"{dt:.2f}" for _, dt, _ in passes)
     return {"value": rates[len(rates) // 2], "unit": "output samples/s", "cores": oracle.num_threads(),
             "kind": "oracle", "host": host_cpu(),
-            "sample": f"{n_src_sample} of the 64 sources with all their {n_rows} (direction, ear) rows "
-                      f"({n_out} outputs), FP64 oracle in chunks of {chunk} sources; median of {reps} timed "
-                      f"passes after a warm-up ({secs} s)"}
+            "sample": f"{n_src_sample} of 64 sources, all {n_rows} rows ({n_out} outputs), in chunks of {chunk} "
+                      f"sources; median of {reps} passes ({secs} s)"}
 
 
 def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
@@ -325,58 +324,80 @@ def spectral_distortion_rows(X, Y) -> np.ndarray:
     return np.sqrt(np.mean((20 * np.log10(A / B)) ** 2, axis=1))
 
 
-def bench_sparsifier(H, hs, fac, lf, lg, k):
-    """Quality of the paper's own sparsifier (L1-NNLS, Eq. (14), with the
-    trained f fixed; lambda searched per filter for at most k taps) against
-    top-k with NNLS refit, on the full 1,250-direction set."""
-    X = hs.h
-    f = fac["f"]
+def filter_scores(X, f, p, g, lg) -> dict:
+    """Reconstruction quality of the tap table (p, g) with resonance f on the
+    HRIR set X: E_dB = 10 log10(sum ||x - f * ghat||^2 / sum ||x||^2) over the
+    set and per filter (worst filter, fraction of filters above -30 dB), the
+    mean spectral distortion of Eq. (17), and the mean count of non-zero taps."""
+    n = X.shape[0]
+    G = np.zeros((n, lg))
+    for i in range(n):
+        np.add.at(G[i], p[i], g[i].astype(np.float64))
+    Y = np.stack([np.convolve(f, G[i]) for i in range(n)])
+    num = np.sum((X - Y) ** 2, axis=1)
+    den = np.sum(X ** 2, axis=1)
+    per = 10 * np.log10(num / den)
+    return {"E_dB": float(10 * np.log10(num.sum() / den.sum())), "E_dB_worst_filter": float(per.max()),
+            "frac_filters_above_-30dB": float(np.mean(per > -30.0)),
+            "SD_dB_mean": float(np.mean(spectral_distortion_rows(X, Y))),
+            "nnze_mean": float(np.mean(np.count_nonzero(G, axis=1)))}
 
-    def scores(p, g):
-        G = np.zeros((X.shape[0], lg))
-        for i in range(X.shape[0]):
-            np.add.at(G[i], p[i], g[i].astype(np.float64))
-        Y = np.stack([np.convolve(f, G[i]) for i in range(X.shape[0])])
-        e = float(10 * np.log10(np.sum((X - Y) ** 2) / np.sum(X ** 2)))
-        return e, float(np.mean(spectral_distortion_rows(X, Y))), float(np.mean(np.count_nonzero(G, axis=1)))
 
-    res = {}
-    e, sd, nz = scores(fac["p"], fac["g"])
-    res["topk_refit"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz}
+def fine_tune(H, X, f, lg, k, fac) -> dict:
+    """Alg. 1's last step with f fixed, at a budget of k taps per filter:
+    top-k of G with the NNLS refit on that support (the library's default),
+    and the paper's own sparsifier, the L1-NNLS of Eq. (14) with lambda
+    searched per filter for at most k taps, with the identity transform and
+    with the window transform of Eq. (16), its bandwidth tuned per HRIR at
+    that sparsity."""
+    res = {"topk_refit": filter_scores(X, f, fac["p"], fac["g"], lg)}
     t = time.perf_counter()
     r = H.sparsify(X, f, k, "I", target_nnze=k)
-    e, sd, nz = scores(r["p"], r["g"])
-    res["l1_nnls_identity"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz, "host_s": time.perf_counter() - t}
-    t = time.perf_counter()
-    grid = [15.0 + 2.0 * i for i in range(25)] + [100.0, 160.0, 250.0, float("inf")]
-    sig, sd_tuned = H.tune_sigma(X, f, grid)
-    _, sd_id = H.tune_sigma(X, f, [float("inf")])
-    # the paper's table: SD at lambda = 0, identity against per-HRIR tuned sigma
-    res["sigma_table_lambda0"] = {"identity_SD_dB_mean": float(np.mean(sd_id)),
-                                  "tuned_SD_dB_mean": float(np.mean(sd_tuned)),
-                                  "relative_drop": float(1 - np.mean(sd_tuned) / np.mean(sd_id))}
-    log(f"sigma tuning at lambda = 0: SD {np.mean(sd_id):.3f} -> {np.mean(sd_tuned):.3f} dB")
-    r = H.sparsify(X, f, k, "W", sigma=sig, target_nnze=k)
-    e, sd, nz = scores(r["p"], r["g"])
-    res["l1_nnls_window_sigma_tuned_at_lambda0"] = {"E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz,
-                                                    "sigma_median": float(np.median(sig)),
-                                                    "host_s": time.perf_counter() - t}
-    # bandwidth tuned at the sparsity the filters will have: per row and
-    # bandwidth, lambda searched for at most k taps, then the lowest SD
+    res["l1_nnls_identity"] = dict(filter_scores(X, f, r["p"], r["g"], lg), host_s=time.perf_counter() - t)
     t = time.perf_counter()
     grid_k = [15.0, 23.0, 35.0, 53.0, 80.0, float("inf")]
     sig_k, _ = H.tune_sigma(X, f, grid_k, target_nnze=k)
     r = H.sparsify(X, f, k, "W", sigma=sig_k, target_nnze=k)
-    e, sd, nz = scores(r["p"], r["g"])
-    res[f"l1_nnls_window_sigma_tuned_at_{k}_taps"] = {
-        "E_dB": e, "SD_dB_mean": sd, "nnze_mean": nz, "sigma_grid": grid_k,
-        "sigma_median": float(np.median(sig_k)), "frac_identity": float(np.mean(np.isinf(sig_k))),
-        "host_s": time.perf_counter() - t}
-    for name, v in res.items():
-        if "E_dB" not in v:
-            continue
-        log(f"sparsifier {name}: E_dB {v['E_dB']:.2f}, SD {v['SD_dB_mean']:.3f} dB, NNZE {v['nnze_mean']:.2f}")
+    res[f"l1_nnls_window_sigma_tuned_at_{k}_taps"] = dict(
+        filter_scores(X, f, r["p"], r["g"], lg), sigma_grid=grid_k, sigma_median=float(np.median(sig_k)),
+        frac_identity=float(np.mean(np.isinf(sig_k))), host_s=time.perf_counter() - t)
     return res
+
+
+def bench_quality(H, hs, fac, lf, lg, k, fact_iters, paper_iters):
+    """Reconstruction quality at K = k kept taps for two orderings of the
+    method on the 1,250-direction set:
+      * the headline's factorization (the L1 weight inside the Alg. 1 loop
+        with a continuation, fact_iters iterations), then the fine-tune step;
+      * Alg. 1 as the paper orders it: plain multiplicative iterations
+        (lambda = 0) for each T in paper_iters (the text's 50, and more),
+        then the fine-tune step with f fixed.
+    Each fine-tune variant reports E_dB over the set, the worst filter, the
+    fraction of filters above -30 dB and the mean SD; the paper's sigma table
+    (SD at lambda = 0, identity against per-HRIR tuned sigma) is given once."""
+    X = hs.h
+    out = {"headline_factorization": f"L1 weight 0.2 inside Alg. 1 with continuation, T = {fact_iters}"}
+    pipes = {f"l1_continuation_T{fact_iters}": fac}
+    for T in paper_iters:
+        t = time.perf_counter()
+        pipes[f"alg1_lambda0_T{T}"] = H.factorize(X, lf, T, k, seed=7, lambda0=0.0, want_cost=False, device=True)
+        log(f"Alg. 1 at lambda = 0, T = {T}: factorized in {time.perf_counter() - t:.2f} s")
+    for name, fc in pipes.items():
+        res = fine_tune(H, X, fc["f"], lg, k, fc)
+        out[name] = res
+        for v, q in res.items():
+            log(f"quality {name} / {v}: E_dB {q['E_dB']:.2f} (worst filter {q['E_dB_worst_filter']:.2f}, "
+                f"{100 * q['frac_filters_above_-30dB']:.1f} % above -30 dB), SD {q['SD_dB_mean']:.3f} dB, "
+                f"NNZE {q['nnze_mean']:.2f}")
+    f = fac["f"]
+    grid = [15.0 + 2.0 * i for i in range(25)] + [100.0, 160.0, 250.0, float("inf")]
+    _, sd_tuned = H.tune_sigma(X, f, grid)
+    _, sd_id = H.tune_sigma(X, f, [float("inf")])
+    out["sigma_table_lambda0"] = {"identity_SD_dB_mean": float(np.mean(sd_id)),
+                                  "tuned_SD_dB_mean": float(np.mean(sd_tuned)),
+                                  "relative_drop": float(1 - np.mean(sd_tuned) / np.mean(sd_id))}
+    log(f"sigma tuning at lambda = 0: SD {np.mean(sd_id):.3f} -> {np.mean(sd_tuned):.3f} dB")
+    return out
 
 
 def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
@@ -572,6 +593,75 @@ def bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens, j
     planR.close()
     return res
 
+HEADLINE_MAX_BYTES = 2048
+
+
+def _r(x, nd=4):
+    """Round a float to nd significant digits (None passes through)."""
+    return None if x is None else float(f"{x:.{nd}g}")
+
+
+def headline(res: dict, detail_path=None) -> dict:
+    """Compact summary of the full result (the last stdout line): metric,
+    value, timing, config, roofline and CPU baseline, plus one or two
+    figures per section.  Every section is optional."""
+    cfg = res.get("config", {})
+    rf = res.get("roofline", {})
+    cpu = res.get("cpu_baseline")
+    out = {k: res.get(k) for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                   "ms_median", "ms_min", "higher_is_better", "scaling", "vs_baseline", "dtype",
+                                   "data")}
+    for k in ("value", "ms_per_step", "ms_median", "ms_min"):
+        out[k] = _r(out[k], 6)
+    out["config"] = {"workload": cfg.get("workload"), "K": cfg.get("K"), "output_samples": cfg.get("output_samples"),
+                     "tile": cfg.get("tile"), "kernel": cfg.get("kernel")}
+    out["roofline"] = {"bound": rf.get("bound"), "achieved": _r(rf.get("achieved"), 5), "peak": rf.get("peak"),
+                       "unit": rf.get("unit"), "frac": _r(rf.get("frac"), 4), "traffic": rf.get("traffic"),
+                       "algorithmic_bytes": rf.get("algorithmic_bytes"), "kernel": rf.get("kernel")}
+    if cpu:
+        host = cpu.get("host", {})
+        out["cpu_baseline"] = {"value": _r(cpu.get("value")), "unit": cpu.get("unit"), "cores": cpu.get("cores"),
+                               "kind": cpu.get("kind"), "host": host.get("model"),
+                               "sample": (cpu.get("sample") or "")[:160]}
+    s = {}
+    legs = res.get("legs") or {}
+    for name, key in (("dense_200", "speedup_sparse"), ("fft_ola", "speedup_sparse"), ("unfused", "speedup_fused")):
+        if name in legs:
+            s[name] = {"ms": _r(legs[name]["ms_per_step"]), key: _r(legs[name][key], 3)}
+    ks = res.get("k_sweep") or {}
+    if ks:
+        s["k_sweep_ms"] = {k: _r(v["ms_per_step"]) for k, v in ks.items()}
+    fz = res.get("factorize") or {}
+    if fz:
+        s["E_dB"] = {"aggregate": _r(fz.get("E_dB_aggregate")), "worst_filter": _r(fz.get("E_dB_worst_filter")),
+                     "frac_above_-30": _r(fz.get("frac_filters_above_-30dB"), 3)}
+    q = res.get("quality") or {}
+    for name, v in q.items():
+        if name.startswith("alg1_") and isinstance(v, dict) and "topk_refit" in v:
+            s["paper_" + name] = {"topk_refit_E_dB": _r(v["topk_refit"]["E_dB"]),
+                                  "l1_nnls_E_dB": _r(v["l1_nnls_identity"]["E_dB"])}
+    un = res.get("uneven")
+    if un:
+        s["uneven"] = {"ms": _r(un["ms_per_step"]), "frac": _r(un["frac_hbm_peak"], 3),
+                       "best_any_shape_ms": _r(un["best_any_shape"]["ms_per_step"])}
+    lat = res.get("block_latency")
+    if lat:
+        s["block_latency_us"] = {"p50": _r(lat["p50_ms"] * 1e3), "p99": _r(lat["p99_ms"] * 1e3)}
+    sv = res.get("serving")
+    if sv:
+        s["serving"] = {"saturation_blocks_per_s": _r(sv["saturation_blocks_per_s"]),
+                        "realtime_p99_us": _r(sv["p99_ms_realtime"] * 1e3)}
+    sg = res.get("surrogate")
+    if sg:
+        ho = sg.get("heldout_E_dB_vs_factorization") or {}
+        s["surrogate"] = {"heldout_frac_below_-30": _r(ho.get("frac_below_-30"), 3),
+                          "fallback_fraction": _r(sg.get("fallback_fraction"), 3),
+                          "moving_ms": _r(sg["moving_render"]["ms_per_step"])}
+    out["summary"] = s
+    if detail_path:
+        out["detail"] = detail_path
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -600,7 +690,12 @@ def main():
     ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds per streaming-loop load level (0: skip)")
-    ap.add_argument("--no-sparsifier", action="store_true", help="skip the L1-NNLS sparsifier quality section")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the reconstruction-quality section (paper's Alg. 1 ordering and sparsifiers)")
+    ap.add_argument("--paper-iters", default="50,2000",
+                    help="iteration counts of plain Alg. 1 (lambda = 0) in the quality section (comma list)")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full result (every section); stdout's last line is the compact headline")
     ap.add_argument("--no-regions", action="store_true", help="skip the per-region resonance section")
     ap.add_argument("--surrogate-steps", type=int, default=12000,
                     help="Adam steps of the surrogate network (multiple of 1000; 0: skip the section)")
@@ -631,10 +726,14 @@ def main():
                       "device_s": t_dev, "host_s": t_host, "host_threads": host_cpu()["affinity"],
                       "max_abs_diff_f": float(np.max(np.abs(fac["f"] - fac_host["f"]))),
                       "same_support": bool(np.array_equal(fac["p"], fac_host["p"]))}
-    del fac_host
     e_all = fac["err_db"]
     energy = np.sum(hs.h ** 2, axis=1)
     e_agg = float(10 * np.log10(np.sum(10 ** (e_all / 10) * energy) / np.sum(energy)))
+    factorize_info.update({"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
+                           "frac_filters_above_-30dB": float(np.mean(e_all > -30.0)),
+                           "method": f"L1 weight 0.2 inside Alg. 1 with continuation, T = {args.fact_iters}, "
+                                     f"then top-{args.k} + NNLS refit"})
+    del fac_host
     log(f"factorized on the GPU in {t_dev:.2f} s (host {t_host:.2f} s, same support "
         f"{factorize_info['same_support']}): E_dB aggregate {e_agg:.2f}, worst {e_all.max():.2f}")
     r = fac["f"].astype(np.float32)
@@ -649,6 +748,10 @@ def main():
     src = torch.from_numpy(np.concatenate(srcs)).to(dev)
     out_off, total = H.row_layout(plan, lens, jobs)
     out = torch.empty(total, dtype=torch.float32, device=dev)
+    # set-up: the first write to each page of a fresh allocation is slower
+    # than later ones; touch the whole buffer once here, before any timing
+    out.zero_()
+    torch.cuda.synchronize()
     flags = (H.SPCONV_PERSISTENT if args.persistent else 0) | {"quad": 0, "lds_gather": H.SPCONV_LDS_GATHER,
                                                                 "regwin": H.SPCONV_REGWIN}[args.kernel]
     batch = H.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], tile=args.tile,
@@ -761,7 +864,8 @@ def main():
     uneven = None if args.no_uneven else bench_uneven(H, torch, dev, fac, r, lf, lg, args)
     latency = bench_latency(H, torch, dev, fac, r, lg, args) if args.latency_ticks > 0 else None
     serving = bench_serving(H, fac, r, lg, args) if args.serve_seconds > 0 else None
-    sparsifier = None if args.no_sparsifier else bench_sparsifier(H, hs, fac, lf, lg, args.k)
+    quality = None if args.no_quality else bench_quality(
+        H, hs, fac, lf, lg, args.k, args.fact_iters, [int(x) for x in args.paper_iters.split(",") if x])
     surrogate = bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args) if args.surrogate_steps > 0 else None
 
     res = {
@@ -796,8 +900,7 @@ def main():
                                 "lds_gather": "k_render_tiles<32,16>"}[info["kernel"]]},
         "write_reference": write_ref,
         "factorize": factorize_info,
-        "quality": {"E_dB_aggregate": e_agg, "E_dB_worst_filter": float(e_all.max()),
-                    "fact_iters": args.fact_iters, "sparsifiers": sparsifier},
+        "quality": quality,
         "legs": legs,
         "k_sweep": k_sweep,
         "regions": regions,
@@ -814,7 +917,13 @@ def main():
         res["cpu_baseline"] = cpu_baseline(r, srcs, fac["p"], fac["g"], lg, jobs, args.cpu_sources)
         log(f"CPU baseline: {res['cpu_baseline']['value']:.3g} output samples/s "
             f"({res['cpu_baseline']['cores']} threads)")
-    print(json.dumps(res), flush=True)
+    detail = args.detail_out
+    if detail:
+        os.makedirs(os.path.dirname(os.path.abspath(detail)), exist_ok=True)
+        with open(detail, "w") as fh:
+            json.dump(res, fh)
+        log(f"full result written to {detail}")
+    print(json.dumps(headline(res, detail)), flush=True)
 
 
 if __name__ == "__main__":

@@ -214,3 +214,24 @@ def test_refit_equals_nnls_on_support():
     for i in range(N):
         ref = scipy_nnls(T[:, p[i, :nnz[i]]], X[i])[0]
         assert np.max(np.abs(gr[i, :nnz[i]] - ref)) < 1e-9
+
+
+def test_cost_is_eq3_frobenius_norm():
+    """or_cost is the objective of Eq. (3), ||X^T - T(f) G^T||_F^2 with T(f)
+    the Toeplitz matrix of Eq. (12): computed here from scipy's Toeplitz
+    constructor and a matrix product (no convolution), it agrees to
+    rounding; G = 0 gives ||X||_F^2, and exact factors give 0."""
+    from scipy.linalg import toeplitz
+    rng = np.random.default_rng(21)
+    for (N, M, lf) in [(6, 12, 4), (4, 30, 7), (3, 5, 5), (2, 9, 1)]:
+        lg = M - lf + 1
+        X = rng.standard_normal((N, M))
+        f = rng.standard_normal(lf)
+        G = rng.uniform(0.0, 1.0, size=(N, lg))
+        T = toeplitz(np.concatenate([f, np.zeros(M - lf)]), np.concatenate([[f[0]], np.zeros(lg - 1)]))
+        assert T.shape == (M, lg)
+        ref = float(np.sum((X.T - T @ G.T) ** 2))
+        assert abs(oracle.cost(X, f, G) - ref) <= 1e-12 * ref
+        assert abs(oracle.cost(X, f, np.zeros_like(G)) - np.sum(X ** 2)) <= 1e-12 * np.sum(X ** 2)
+        Xe = (T @ G.T).T
+        assert oracle.cost(Xe, f, G) <= 1e-24 * np.sum(Xe ** 2)

@@ -47,3 +47,31 @@ def test_segments_and_fades_follow_the_static_renders(n, seg, fade):
             a = (u + 1) / fade
             want = a * want + (1 - a) * stat[filt[j - 1]][t]
         assert abs(y[t] - want) <= 1e-12 * (1 + abs(want)), t
+
+
+@pytest.mark.parametrize("fade", [64, 17, 1])
+def test_crossfade_weight_is_a_linear_ramp(fade):
+    """The crossfade is linear over `fade` samples: with a zero filter after
+    the change, out = (1 - a(u)) y_old, so a(u) can be read off the output;
+    it must rise by exactly 1/fade per sample and reach 1 (the new filter
+    alone) at the fade's last sample.  Swapping the two filters gives
+    weights a(u) and 1 - a(u) the other way round, so the two outputs add
+    up to the sum of the static renders at every sample."""
+    n, seg = 1024, 256
+    r, p, g, s, _ = _setup(40 + fade, n)
+    g = g.copy()
+    g[0] = 0.0                                        # filter 0: no taps
+    filt = np.array([3, 0, 3, 0], dtype=np.int32)
+    y = oracle.moving_render(r, s, p, g, LG, filt, seg, fade)
+    y_old = oracle.sparse_render(r, s, p[3], g[3], LG)
+    u = np.arange(fade)
+    t = seg + u                                       # the first fade (3 -> 0)
+    ok = np.abs(y_old[t]) > 1e-3 * np.max(np.abs(y_old))
+    a = 1.0 - y[t][ok] / y_old[t][ok]
+    assert np.allclose(a, (u[ok] + 1) / fade, rtol=0, atol=1e-9)
+    assert abs(y[seg + fade - 1]) <= 1e-12 * np.max(np.abs(y_old))
+    ya = oracle.moving_render(r, s, p, g, LG, np.array([3, 5, 3, 5], np.int32), seg, fade)
+    yb = oracle.moving_render(r, s, p, g, LG, np.array([5, 3, 5, 3], np.int32), seg, fade)
+    y5 = oracle.sparse_render(r, s, p[5], g[5], LG)
+    tt = np.arange(seg, n)
+    assert np.max(np.abs(ya[tt] + yb[tt] - y_old[tt] - y5[tt])) <= 1e-12 * np.max(np.abs(y_old))
