@@ -29,8 +29,20 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "output samples/s, sparse K=16 vs dense 200-tap on 1 GPU; p99 block latency"
 
 
+_LOG_FILE = []   # the full progress log (opened in main next to the detail file)
+
+
+def note(msg):
+    """A progress line for the log file only (stderr stays short: the
+    headline JSON on stdout is read from the tail of both streams)."""
+    for fh in _LOG_FILE:
+        print(f"[bench] {msg}", file=fh, flush=True)
+
+
 def log(msg):
+    """A progress line for stderr and the log file."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    note(msg)
 
 
 def kernel_source_hash() -> str:
@@ -220,7 +232,7 @@ def bench_latency(H, torch, dev, fac, r, lg, args):
         st.render(pool, jt, out)
         ev[t][1].record(cur)
         if t % 2000 == 1999:
-            log(f"latency: {t + 1} launches")
+            note(f"latency: {t + 1} launches")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
@@ -263,7 +275,7 @@ def bench_serving(H, fac, r, lg, args):
         # its own schedule, so the tail is the generator's, not the loop's
         st["generator_limited"] = bool(st["p99_admit_ms"] > 1.0 and st["eagain"] < 0.001 * st["blocks"])
         runs.append(st)
-        log(f"serving {label}: {st['achieved_hz']:.4g} blocks/s, {st['out_samples_per_s']:.3g} samples/s, "
+        note(f"serving {label}: {st['achieved_hz']:.4g} blocks/s, {st['out_samples_per_s']:.3g} samples/s, "
             f"p50 {st['p50_ms'] * 1e3:.0f} us, p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f} "
             f"(p99 parts: admit {st['p99_admit_ms'] * 1e3:.0f}, server {st['p99_server_ms'] * 1e3:.0f}, "
             f"collect {st['p99_collect_ms'] * 1e3:.0f} us)" + (" [generator-limited]" if st["generator_limited"] else ""))
@@ -283,7 +295,7 @@ def bench_serving(H, fac, r, lg, args):
                         "p99_ms": med["p99_ms"], "p99_ms_runs": [st["p99_ms"] for st in reps],
                         "generator_limited": med["generator_limited"]}
         p99s = ", ".join("%.0f" % (st["p99_ms"] * 1e3) for st in reps)
-        log(f"serving {label}: median run p99 {med['p99_ms'] * 1e3:.0f} us (runs {p99s} us)")
+        note(f"serving {label}: median run p99 {med['p99_ms'] * 1e3:.0f} us (runs {p99s} us)")
     rt = run("real time", rt_hz, 9)
     info = srv.info()
     srv.close()
@@ -291,7 +303,11 @@ def bench_serving(H, fac, r, lg, args):
     direct.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)
     dsat = direct.loadgen(sig, rate_hz=0, duration_s=secs, seed=2, **gen)
     direct.close()
-    log(f"serving direct-launch saturation: {dsat['achieved_hz']:.4g} blocks/s")
+    log(f"serving: saturation {sat_hz:.4g} blocks/s; p99 by load " +
+        ", ".join(f"{k.split()[1]} {v['p99_ms'] * 1e3:.0f} us" + ("*" if v["generator_limited"] else "")
+                  for k, v in sweep.items()) +
+        f" (* generator-limited); real time p50/p99 {rt['p50_ms'] * 1e3:.0f}/{rt['p99_ms'] * 1e3:.0f} us")
+    note(f"serving direct-launch saturation: {dsat['achieved_hz']:.4g} blocks/s")
     # the zero-copy ring: no copy commands per generation
     zc = H.Server(plan, n_streams, hbm_budget=1 << 30, flags=H.STREAM_ZERO_COPY)
     zc.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)
@@ -302,7 +318,7 @@ def bench_serving(H, fac, r, lg, args):
     plan.close()
     for label, st in zruns.items():
         st["label"] = label
-        log(f"serving zero-copy {label}: {st['achieved_hz']:.4g} blocks/s, p50 {st['p50_ms'] * 1e3:.0f} us, "
+        note(f"serving zero-copy {label}: {st['achieved_hz']:.4g} blocks/s, p50 {st['p50_ms'] * 1e3:.0f} us, "
             f"p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f}")
     return {"workload": "1,024 streams at 48 kHz, blocks U{64..1024} samples, Poisson arrivals, K=16, "
                         "1,250 directions; arrival -> output in host memory",
@@ -381,14 +397,16 @@ def bench_quality(H, hs, fac, lf, lg, k, fact_iters, paper_iters):
     for T in paper_iters:
         t = time.perf_counter()
         pipes[f"alg1_lambda0_T{T}"] = H.factorize(X, lf, T, k, seed=7, lambda0=0.0, want_cost=False, device=True)
-        log(f"Alg. 1 at lambda = 0, T = {T}: factorized in {time.perf_counter() - t:.2f} s")
+        note(f"Alg. 1 at lambda = 0, T = {T}: factorized in {time.perf_counter() - t:.2f} s")
     for name, fc in pipes.items():
         res = fine_tune(H, X, fc["f"], lg, k, fc)
         out[name] = res
         for v, q in res.items():
-            log(f"quality {name} / {v}: E_dB {q['E_dB']:.2f} (worst filter {q['E_dB_worst_filter']:.2f}, "
-                f"{100 * q['frac_filters_above_-30dB']:.1f} % above -30 dB), SD {q['SD_dB_mean']:.3f} dB, "
-                f"NNZE {q['nnze_mean']:.2f}")
+            note(f"quality {name} / {v}: E_dB {q['E_dB']:.2f} (worst filter {q['E_dB_worst_filter']:.2f}, "
+                 f"{100 * q['frac_filters_above_-30dB']:.1f} % above -30 dB), SD {q['SD_dB_mean']:.3f} dB, "
+                 f"NNZE {q['nnze_mean']:.2f}")
+        log(f"quality {name}: E_dB " + ", ".join(f"{v} {q['E_dB']:.1f} (worst {q['E_dB_worst_filter']:.1f})"
+                                                 for v, q in res.items()))
     f = fac["f"]
     grid = [15.0 + 2.0 * i for i in range(25)] + [100.0, 160.0, 250.0, float("inf")]
     _, sd_tuned = H.tune_sigma(X, f, grid)
@@ -587,8 +605,10 @@ def bench_regions(H, torch, dev, args, n_src, ns, dps, lf, lg, src, off, lens, j
         ms, _ = time_launches(lambda: b.render(src, out), args.steps, args.warmup)
         res[name + "_render"] = {"ms_per_step": ms, "value": n_out / (ms * 1e-3),
                                  "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "tiles": b.info()["tiles"]}
-        log(f"regions render {name}: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s")
+        note(f"regions render {name}: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s")
         b.close()
+    log(f"regions render: one f {res['one_f_render']['ms_per_step']:.3f} ms/step, three regions "
+        f"{res['three_regions_render']['ms_per_step']:.3f} ms/step")
     plan1.close()
     planR.close()
     return res
@@ -706,6 +726,9 @@ def main():
         print(json.dumps({"error": "the renderer runs on one GPU only (the multi-GPU layout is a design note); run with --gpus 1"}))
         sys.exit(2)
 
+    if args.detail_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+        _LOG_FILE.append(open(os.path.splitext(args.detail_out)[0] + "_log.txt", "w"))
     import torch
     sys.path.insert(0, ROOT)
     import paper_1502_03162_amd as H
@@ -815,10 +838,11 @@ def main():
             fo = H.FftOla(hs.h.astype(np.float32), nfft, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)])
             fms, _ = time_launches(lambda: fo.render(src, out), args.leg_steps, 1)
             by[str(nfft)] = fms
-            log(f"FFT overlap-add nfft={nfft}: {fms:.3f} ms/step, {n_out / (fms * 1e-3):.4g} samples/s")
+            note(f"FFT overlap-add nfft={nfft}: {fms:.3f} ms/step, {n_out / (fms * 1e-3):.4g} samples/s")
             fo.close()
             torch.cuda.empty_cache()
         best = min(by, key=by.get)
+        log(f"FFT overlap-add: best nfft {best}, {by[best]:.3f} ms/step, sparse speedup {by[best] / ms:.2f}x")
         legs["fft_ola"] = {"ms_per_step": by[best], "value": n_out / (by[best] * 1e-3), "best_nfft": int(best),
                            "ms_by_nfft": by, "speedup_sparse": by[best] / ms}
 
