@@ -278,6 +278,28 @@ int spconv_render(const hrir_plan* plan, const float* d_src, int64_t src_elems, 
                   const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs,
                   float* d_out, int64_t out_elems, void* stream);
 
+/* Allocation-free one-shot render, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernel, tiling and results (bit for
+ * bit) as spconv_render, which allocates a descriptor table per call; here
+ * the tile and job descriptors go into one fixed device array of the
+ * library (2.25 MiB per device, held until the process ends), staged from
+ * fixed host arrays.  The call makes no device or host allocation, is
+ * synchronous (it waits for `stream` before returning), and calls from
+ * several host threads are serialised by a lock; the array keeps the last
+ * call's descriptors.  The current device must be the plan's.
+ * Limits: n_jobs <= SPCONV_NOALLOC_MAX_JOBS, and at most
+ * SPCONV_NOALLOC_MAX_TILES tiles of 2048 outputs, where a source with
+ * output length L (= src_len + lf + lg - 2) and any number of jobs counts
+ * ceil(L / 2048) tiles (per resonance region of its jobs).
+ * Errors: EINVAL (as spconv_render, and either limit exceeded, checked
+ * before any device work), EDEVICE. */
+#define SPCONV_NOALLOC_MAX_JOBS 16384
+#define SPCONV_NOALLOC_MAX_TILES 65536
+int spconv_render_noalloc(const hrir_plan* plan, const float* d_src, int64_t src_elems, const int64_t* src_off,
+                          const int64_t* src_len, int32_t n_src, const spconv_job* jobs, int32_t n_jobs,
+                          float* d_out, int64_t out_elems, void* stream);
+
 /* ------------------------------------------------------------------------
  * Dense direct render: the comparison leg, out = s * h with a full HRIR
  * (direct convolution costs the filter length per output, Sec. IV-F).

@@ -115,6 +115,8 @@ def _load() -> ctypes.CDLL:
         "spconv_batch_destroy": (None, [c_void_p]),
         "spconv_render": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
                                   c_void_p, c_int64, c_void_p]),
+        "spconv_render_noalloc": (c_int, [c_void_p, c_void_p, c_int64, P_i64, P_i64, c_int32, POINTER(SpconvJob),
+                                          c_int32, c_void_p, c_int64, c_void_p]),
         "dense_plan": (c_int, [P_f, c_int32, c_int32, POINTER(c_void_p)]),
         "dense_plan_destroy": (None, [c_void_p]),
         "dense_batch_create": (c_int, [c_void_p, P_i64, P_i64, c_int32, POINTER(SpconvJob), c_int32,
@@ -170,7 +172,7 @@ def _load() -> ctypes.CDLL:
 
 _lib = _load()
 EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_multi", "spconv_plan_destroy", "spconv_batch_create",
-            "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "dense_plan",
+            "spconv_batch_render", "spconv_batch_info", "spconv_batch_destroy", "spconv_render", "spconv_render_noalloc", "dense_plan",
             "dense_plan_destroy", "dense_batch_create", "dense_batch_render", "dense_batch_destroy", "fftola_create",
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
@@ -421,6 +423,22 @@ def render(plan: Plan, src, src_off, src_len, jobs, out, stream=None):
     op, on = _f32(out)
     _check(_lib.spconv_render(plan.handle, sp, sn, _ptr(src_off, c_int64), _ptr(src_len, c_int64), src_len.size,
                               jobs, n, op, on, c_void_p(_stream_handle(stream))))
+
+
+def render_noalloc(plan: Plan, src, src_off, src_len, jobs, out, stream=None):
+    """One-shot synchronous render that allocates nothing
+    (spconv_render_noalloc): same results as render()."""
+    src_off = np.ascontiguousarray(src_off, dtype=np.int64)
+    src_len = np.ascontiguousarray(src_len, dtype=np.int64)
+    jobs, n = make_jobs(jobs)
+    sp, sn = _f32(src)
+    op, on = _f32(out)
+    _check(_lib.spconv_render_noalloc(plan.handle, sp, sn, _ptr(src_off, c_int64), _ptr(src_len, c_int64),
+                                      src_len.size, jobs, n, op, on, c_void_p(_stream_handle(stream))))
+
+
+NOALLOC_MAX_JOBS = 16384
+NOALLOC_MAX_TILES = 65536
 
 
 # ---------------------------------------------------------------------------

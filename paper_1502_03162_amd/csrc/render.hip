@@ -435,6 +435,70 @@ extern "C" void spconv_plan_destroy(hrir_plan* plan) {
     delete plan;
 }
 
+namespace {
+
+// Source and job-list checks shared by the batch and one-shot entry points.
+int check_jobs(const hrir_plan* plan, const int64_t* src_off, const int64_t* src_len, int32_t n_src,
+               const spconv_job* jobs, int32_t n_jobs, const char* who) {
+    const int lf = plan->lf, lg = plan->lg;
+    for (int i = 0; i < n_src; ++i) {
+        if (src_len[i] < 1 || src_len[i] > (int64_t)INT32_MAX - lf - lg)
+            return fail(HRIR_EINVAL, "%s: src_len[%d]=%lld out of range", who, i, (long long)src_len[i]);
+        if (src_off[i] < 0) return fail(HRIR_EINVAL, "%s: src_off[%d] < 0", who, i);
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].src < 0 || jobs[j].src >= n_src)
+            return fail(HRIR_EINVAL, "%s: job %d source %d out of range", who, j, jobs[j].src);
+        if (jobs[j].filt < 0 || jobs[j].filt >= plan->n_filters)
+            return fail(HRIR_EINVAL, "%s: job %d filter %d out of range", who, j, jobs[j].filt);
+        if (jobs[j].out_off < 0) return fail(HRIR_EINVAL, "%s: job %d out_off < 0", who, j);
+    }
+    return HRIR_OK;
+}
+
+int job_region(const hrir_plan* plan, int filt) { return plan->n_res > 1 ? plan->res[filt] : 0; }
+
+// Job indices grouped by source, then by region, keeping list order inside a
+// group: a tile's jobs share one z = r_region * s.  In place (no allocation).
+void order_jobs(const hrir_plan* plan, const spconv_job* jobs, int n_jobs, int* order) {
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::sort(order, order + n_jobs, [&](int a, int c) {
+        if (jobs[a].src != jobs[c].src) return jobs[a].src < jobs[c].src;
+        const int ra = job_region(plan, jobs[a].filt), rc = job_region(plan, jobs[c].filt);
+        if (ra != rc) return ra < rc;
+        return a < c;
+    });
+}
+
+// Calls run(s, region, j0, j1) for each run [j0, j1) of ordered jobs that
+// share a source and a region.
+template <class F>
+void for_each_run(const hrir_plan* plan, const spconv_job* jobs, const int* order, int n_jobs, F&& run) {
+    for (int j0 = 0; j0 < n_jobs;) {
+        const int s = jobs[order[j0]].src;
+        const int rg = job_region(plan, jobs[order[j0]].filt);
+        int j1 = j0;
+        while (j1 < n_jobs && jobs[order[j1]].src == s && job_region(plan, jobs[order[j1]].filt) == rg) ++j1;
+        run(s, rg, j0, j1);
+        j0 = j1;
+    }
+}
+
+// Largest work first: the hardware dispatcher (or the persistent queue) then
+// finishes a ragged job mix with small tiles at the end.  Equal work keeps
+// the creation order (job range, then time), so the order is unique.
+void order_tiles(TileDesc* t, int64_t n, int tile) {
+    std::sort(t, t + n, [tile](const TileDesc& a, const TileDesc& c) {
+        const int64_t wa = (int64_t)a.job_count * std::min<int64_t>(tile, a.out_len - a.t0);
+        const int64_t wc = (int64_t)c.job_count * std::min<int64_t>(tile, c.out_len - c.t0);
+        if (wa != wc) return wa > wc;
+        if (a.job_begin != c.job_begin) return a.job_begin < c.job_begin;
+        return a.t0 < c.t0;
+    });
+}
+
+}  // namespace
+
 extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off, const int64_t* src_len,
                                    int32_t n_src, const spconv_job* jobs, int32_t n_jobs, int32_t tile,
                                    int32_t group, int32_t flags, hrir_batch** out) {
@@ -468,18 +532,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return fail(HRIR_EINVAL, "spconv_batch_create: a plan with %d resonance filters needs the default kernel",
                     plan->n_res);
     const int lf = plan->lf, lg = plan->lg;
-    for (int i = 0; i < n_src; ++i) {
-        if (src_len[i] < 1 || src_len[i] > (int64_t)INT32_MAX - lf - lg)
-            return fail(HRIR_EINVAL, "spconv_batch_create: src_len[%d]=%lld out of range", i, (long long)src_len[i]);
-        if (src_off[i] < 0) return fail(HRIR_EINVAL, "spconv_batch_create: src_off[%d] < 0", i);
-    }
-    for (int j = 0; j < n_jobs; ++j) {
-        if (jobs[j].src < 0 || jobs[j].src >= n_src)
-            return fail(HRIR_EINVAL, "spconv_batch_create: job %d source %d out of range", j, jobs[j].src);
-        if (jobs[j].filt < 0 || jobs[j].filt >= plan->n_filters)
-            return fail(HRIR_EINVAL, "spconv_batch_create: job %d filter %d out of range", j, jobs[j].filt);
-        if (jobs[j].out_off < 0) return fail(HRIR_EINVAL, "spconv_batch_create: job %d out_off < 0", j);
-    }
+    if (int rc = check_jobs(plan, src_off, src_len, n_src, jobs, n_jobs, "spconv_batch_create")) return rc;
     auto* b = new (std::nothrow) hrir_batch;
     if (!b) return fail(HRIR_ENOMEM, "spconv_batch_create: out of host memory");
     b->plan = plan; b->flags = flags; b->TB = tile; b->n_jobs = n_jobs; b->kind = kind;
@@ -488,15 +541,8 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         b->src_extent = std::max(b->src_extent, src_off[s] + src_len[s]);
         b->out_extent = std::max(b->out_extent, jobs[j].out_off + src_len[s] + lf + lg - 2);
     }
-    // Jobs grouped by source, then by region (stable, so a group's jobs keep
-    // their order): a tile's jobs share one z = r_region * s.
-    auto region = [plan](int filt) { return plan->n_res > 1 ? plan->res[filt] : 0; };
     std::vector<int> order(n_jobs);
-    for (int j = 0; j < n_jobs; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        if (jobs[a].src != jobs[c].src) return jobs[a].src < jobs[c].src;
-        return region(jobs[a].filt) < region(jobs[c].filt);
-    });
+    order_jobs(plan, jobs, n_jobs, order.data());
     std::vector<JobDesc> hj(n_jobs);
     for (int j = 0; j < n_jobs; ++j) hj[j] = JobDesc{jobs[order[j]].out_off, jobs[order[j]].filt, 0};
     std::vector<TileDesc> ht;
@@ -504,11 +550,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     std::vector<GDesc> hg;
     int64_t zsize = 0;
     int max_group = 0;
-    for (int j0 = 0; j0 < n_jobs;) {
-        const int s = jobs[order[j0]].src;
-        const int rg = region(jobs[order[j0]].filt);
-        int j1 = j0;
-        while (j1 < n_jobs && jobs[order[j1]].src == s && region(jobs[order[j1]].filt) == rg) ++j1;
+    for_each_run(plan, jobs, order.data(), n_jobs, [&](int s, int rg, int j0, int j1) {
         const int njs = j1 - j0;
         const int gsz = group > 0 ? std::min(group, njs) : njs;
         max_group = std::max(max_group, gsz);
@@ -526,15 +568,8 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
                     hg.push_back(GDesc{hj[j].out_off, zsize, (int32_t)out_len, (int32_t)nz, (int32_t)t0, hj[j].filt});
             zsize += round_up((int)std::min<int64_t>(nz, INT32_MAX - 64), 64);
         }
-        j0 = j1;
-    }
-    // Largest work first: the hardware dispatcher (or the persistent queue)
-    // then finishes a ragged job mix with small tiles at the end.
-    std::stable_sort(ht.begin(), ht.end(), [tile](const TileDesc& a, const TileDesc& c) {
-        const int64_t wa = (int64_t)a.job_count * std::min<int64_t>(tile, a.out_len - a.t0);
-        const int64_t wc = (int64_t)c.job_count * std::min<int64_t>(tile, c.out_len - c.t0);
-        return wa > wc;
     });
+    order_tiles(ht.data(), (int64_t)ht.size(), tile);
     b->n_tiles = (int64_t)ht.size();
     b->group = max_group;
     b->lds_bytes = kind == KIND_REGWIN ? (size_t)rw_lds_bytes(tile, plan->lfp)
@@ -647,5 +682,112 @@ extern "C" int spconv_render(const hrir_plan* plan, const float* d_src, int64_t 
     free_batch(b);
     if (rc) return rc;
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "spconv_render: %s", hipGetErrorString(e));
+    return HRIR_OK;
+}
+
+// ===========================================================================
+// Allocation-free one-shot render: the tile and job descriptors of
+// spconv_render live in a fixed device array instead of a batch's hipMalloc'd
+// table, for callers that cannot allocate device memory.
+// ===========================================================================
+namespace {
+
+constexpr size_t kNaJobBytes = sizeof(JobDesc) * SPCONV_NOALLOC_MAX_JOBS;
+constexpr size_t kNaBytes = kNaJobBytes + sizeof(TileDesc) * SPCONV_NOALLOC_MAX_TILES;
+constexpr int kNaMaxDevices = 64;
+static_assert(kNaJobBytes % 256 == 0, "tile descriptors start 256-byte aligned");
+
+// Host-side state, all guarded by na_mutex: the device address of `scratch`
+// on each device (from hipGetSymbolAddress on the first call there), and the
+// host staging of the descriptors (static, so no call allocates).
+std::mutex na_mutex;
+unsigned char* na_dev[kNaMaxDevices];
+int na_order[SPCONV_NOALLOC_MAX_JOBS];
+JobDesc na_jobs[SPCONV_NOALLOC_MAX_JOBS];
+TileDesc na_tiles[SPCONV_NOALLOC_MAX_TILES];
+
+}  // namespace
+
+// Job descriptors at offset 0, tile descriptors after them.  Host code never
+// passes this name to a kernel or a copy: it uses the address returned by
+// hipGetSymbolAddress for the current device.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+extern "C" int spconv_render_noalloc(const hrir_plan* plan, const float* d_src, int64_t src_elems,
+                                     const int64_t* src_off, const int64_t* src_len, int32_t n_src,
+                                     const spconv_job* jobs, int32_t n_jobs, float* d_out, int64_t out_elems,
+                                     void* stream) {
+    static const char* who = "spconv_render_noalloc";
+    clear_error();
+    if (!plan || (n_src > 0 && (!src_off || !src_len)) || (n_jobs > 0 && !jobs))
+        return fail(HRIR_EINVAL, "%s: null pointer", who);
+    if (n_src < 0 || n_jobs < 0) return fail(HRIR_EINVAL, "%s: negative count", who);
+    if (n_jobs > SPCONV_NOALLOC_MAX_JOBS)
+        return fail(HRIR_EINVAL, "%s: %d jobs exceed the limit of %d", who, n_jobs, SPCONV_NOALLOC_MAX_JOBS);
+    if (int rc = check_jobs(plan, src_off, src_len, n_src, jobs, n_jobs, who)) return rc;
+    if (n_jobs == 0) return HRIR_OK;
+    const int lf = plan->lf, lg = plan->lg, tile = 2048;
+    const size_t lds_bytes = (size_t)quad_lds_bytes(tile, lg, plan->lfp);
+    if (lds_bytes > 160 * 1024) return fail(HRIR_EINVAL, "%s: lg %d needs %zu B of LDS (> 160 KiB)", who, lg, lds_bytes);
+
+    std::lock_guard<std::mutex> lock(na_mutex);
+    // the limits and the buffer extents are checked before any device work
+    order_jobs(plan, jobs, n_jobs, na_order);
+    int64_t n_tiles = 0;
+    for_each_run(plan, jobs, na_order, n_jobs, [&](int s, int, int, int) {
+        n_tiles += (src_len[s] + lf + lg - 2 + tile - 1) / tile;
+    });
+    if (n_tiles > SPCONV_NOALLOC_MAX_TILES)
+        return fail(HRIR_EINVAL, "%s: %lld tiles of %d outputs exceed the limit of %d", who, (long long)n_tiles, tile,
+                    SPCONV_NOALLOC_MAX_TILES);
+    if (!d_src || !d_out) return fail(HRIR_EINVAL, "%s: null device pointer", who);
+    int64_t src_extent = 0, out_extent = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const int s = jobs[j].src;
+        src_extent = std::max(src_extent, src_off[s] + src_len[s]);
+        out_extent = std::max(out_extent, jobs[j].out_off + src_len[s] + lf + lg - 2);
+    }
+    if (src_elems < src_extent || out_elems < out_extent)
+        return fail(HRIR_EINVAL, "%s: buffers too small (src %lld < %lld or out %lld < %lld)", who,
+                    (long long)src_elems, (long long)src_extent, (long long)out_elems, (long long)out_extent);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(HRIR_EINVAL, "%s: device %d >= %d", who, dev, kNaMaxDevices);
+    if (dev != plan->device) return fail(HRIR_EINVAL, "%s: current device %d, plan on %d", who, dev, plan->device);
+    if (!na_dev[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        na_dev[dev] = static_cast<unsigned char*>(ptr);
+    }
+    JobDesc* d_jobs = reinterpret_cast<JobDesc*>(na_dev[dev]);
+    TileDesc* d_tiles = reinterpret_cast<TileDesc*>(na_dev[dev] + kNaJobBytes);
+
+    for (int j = 0; j < n_jobs; ++j) na_jobs[j] = JobDesc{jobs[na_order[j]].out_off, jobs[na_order[j]].filt, 0};
+    int64_t nt = 0;
+    for_each_run(plan, jobs, na_order, n_jobs, [&](int s, int rg, int j0, int j1) {
+        const int64_t out_len = src_len[s] + lf + lg - 2;
+        for (int64_t t0 = 0; t0 < out_len; t0 += tile)
+            na_tiles[nt++] = TileDesc{src_off[s], (int32_t)src_len[s], (int32_t)out_len, (int32_t)t0, j0, j1 - j0, rg};
+    });
+    order_tiles(na_tiles, nt, tile);
+
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int grid = 0;
+    if (int rc = quad_prepare(plan->lfp, plan->kp, lds_bytes, false, nt, &grid)) return rc;
+    // the staging arrays and the device descriptors are reused by the next
+    // call: whatever happens, wait for this one before the lock is released
+    hipError_t e = hipMemcpyAsync(d_jobs, na_jobs, sizeof(JobDesc) * (size_t)n_jobs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_tiles, na_tiles, sizeof(TileDesc) * (size_t)nt, hipMemcpyHostToDevice, st);
+    int rc = HRIR_OK;
+    if (e == hipSuccess) {
+        rc = quad_launch(plan->lfp, plan->kp, false, grid, lds_bytes, st, d_src, d_tiles, (int)nt, d_jobs, plan->d_r,
+                         plan->d_p, plan->d_g, d_out, lg, tile, nullptr);
+        if (rc == HRIR_OK) e = hipGetLastError();
+    }
+    const hipError_t es = hipStreamSynchronize(st);
+    if (rc) return rc;
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return fail(HRIR_EDEVICE, "%s: %s", who, hipGetErrorString(e));
     return HRIR_OK;
 }
