@@ -172,10 +172,17 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
     n_out = sum(plan.out_len(lens[s]) for s, _ in jobs)
     ms, _ = time_launches(lambda: batch.render(src, out), args.steps, args.warmup)
     alg = 4.0 * n_out + 4.0 * float(lens.sum())
-    log(f"uneven: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s, tile {best['tile']} group {best['group']} "
-        f"(autotune {tune_s:.1f} s, best candidate {best['ms']:.3f} ms)")
     info = batch.info()
     batch.close()
+    # the fastest shape of any launch form, timed the same way (graph replay)
+    fb = H.Batch(plan, off, lens, rows, tile=free_best["tile"], group=free_best["group"],
+                 flags=free_best["flags"] | H.SPCONV_GRAPH)
+    free_ms, _ = time_launches(lambda: fb.render(src, out), args.steps, args.warmup)
+    fb.close()
+    log(f"uneven: {ms:.3f} ms/step, {n_out / (ms * 1e-3):.4g} samples/s, tile {best['tile']} group {best['group']} "
+        f"{'256' if best['flags'] & H.SPCONV_WG256 else '512'} threads (autotune {tune_s:.1f} s); best shape of any "
+        f"launch form {free_ms:.3f} ms (tile {free_best['tile']}, group {free_best['group']}, flags "
+        f"{free_best['flags']})")
     del out, src
     torch.cuda.empty_cache()
     return {"workload": "512 pink sources, lengths log-uniform in [4096, 1048576], 1..8 directions x 2 ears, K=16, "
@@ -183,10 +190,12 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
             "output_samples": n_out, "rows": len(jobs), "ms_per_step": ms, "value": n_out / (ms * 1e-3),
             "unit": "output samples/s", "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
             "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile": best["tile"], "group": best["group"],
+            "threads_per_workgroup": 256 if best["flags"] & H.SPCONV_WG256 else 512,
             "persistent_grid": info["grid"], "tiles": info["tiles"], "autotune_s": tune_s,
             "best_any_shape": {"tile": free_best["tile"], "group": free_best["group"],
                                "persistent": bool(free_best["flags"] & H.SPCONV_PERSISTENT),
-                               "ms_per_step": free_best["ms"]}}
+                               "threads_per_workgroup": 256 if free_best["flags"] & H.SPCONV_WG256 else 512,
+                               "ms_per_step": free_ms, "autotune_ms": free_best["ms"]}}
 
 
 def bench_latency(H, torch, dev, fac, r, lg, args):
@@ -263,22 +272,30 @@ def bench_serving(H, fac, r, lg, args):
     sig = synth.pink(4343, 1 << 20)
     rt_hz = n_streams * 48000 / 544.0            # mean block length (64 + 1024) / 2
     srv = H.Server(plan, n_streams, hbm_budget=1 << 30)
-    gen = dict(n_streams=n_streams, block_min=64, block_max=1024, n_filters=2 * 1250, submit_threads=1)
+    # four submitting threads over disjoint stream ranges: one thread cannot
+    # keep a Poisson schedule near the loop's saturation rate
+    gen = dict(n_streams=n_streams, block_min=64, block_max=1024, n_filters=2 * 1250, submit_threads=4)
     srv.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)          # warm-up
     runs = []
 
     def run(label, rate, seed):
         st = srv.loadgen(sig, rate_hz=rate, duration_s=secs, seed=seed, **gen)
         st["label"] = label
-        # arrivals that waited over 1 ms to be admitted while the server
-        # refused (almost) nothing: the single submitting thread fell behind
-        # its own schedule, so the tail is the generator's, not the loop's
-        st["generator_limited"] = bool(st["p99_admit_ms"] > 1.0 and st["eagain"] < 0.001 * st["blocks"])
+        # saturated: the loop refused at least 0.1 % of the blocks (its ring
+        # was full), so arrivals queue behind back-pressure -- the loop's own
+        # limit, expected at and above 100 % load.  generator-limited: the
+        # generator fell behind its own schedule (blocks first offered over
+        # 1 ms after their arrival) while the loop refused (almost) nothing,
+        # so the tail is the generator's, not the loop's.
+        st["saturated"] = bool(st["eagain"] >= 0.001 * st["blocks"])
+        st["generator_limited"] = bool(st["p99_gen_lag_ms"] > 1.0 and not st["saturated"])
         runs.append(st)
         note(f"serving {label}: {st['achieved_hz']:.4g} blocks/s, {st['out_samples_per_s']:.3g} samples/s, "
-            f"p50 {st['p50_ms'] * 1e3:.0f} us, p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f} "
-            f"(p99 parts: admit {st['p99_admit_ms'] * 1e3:.0f}, server {st['p99_server_ms'] * 1e3:.0f}, "
-            f"collect {st['p99_collect_ms'] * 1e3:.0f} us)" + (" [generator-limited]" if st["generator_limited"] else ""))
+             f"p50 {st['p50_ms'] * 1e3:.0f} us, p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f} "
+             f"(p99 parts: admit {st['p99_admit_ms'] * 1e3:.0f} (generator lag {st['p99_gen_lag_ms'] * 1e3:.0f}), "
+             f"server {st['p99_server_ms'] * 1e3:.0f}, collect {st['p99_collect_ms'] * 1e3:.0f} us; "
+             f"refused {st['eagain']})" + (" [generator-limited]" if st["generator_limited"] else "") +
+             (" [saturated]" if st["saturated"] else ""))
         return st
 
     sat = run("saturation", 0, 2)
@@ -292,8 +309,10 @@ def bench_serving(H, fac, r, lg, args):
         reps = [run(f"{label} #{k}", frac * sat_hz, 3 + i + 100 * k) for k in range(3)]
         med = sorted(reps, key=lambda st: st["p99_ms"])[1]
         sweep[label] = {"offered_hz": frac * sat_hz, "achieved_hz": med["achieved_hz"], "p50_ms": med["p50_ms"],
-                        "p99_ms": med["p99_ms"], "p99_ms_runs": [st["p99_ms"] for st in reps],
-                        "generator_limited": med["generator_limited"]}
+                        "p99_ms": med["p99_ms"], "p99_server_ms": med["p99_server_ms"],
+                        "p99_admit_ms": med["p99_admit_ms"], "p99_gen_lag_ms": med["p99_gen_lag_ms"],
+                        "refused": med["eagain"], "p99_ms_runs": [st["p99_ms"] for st in reps],
+                        "generator_limited": med["generator_limited"], "saturated": med["saturated"]}
         p99s = ", ".join("%.0f" % (st["p99_ms"] * 1e3) for st in reps)
         note(f"serving {label}: median run p99 {med['p99_ms'] * 1e3:.0f} us (runs {p99s} us)")
     rt = run("real time", rt_hz, 9)
@@ -303,10 +322,11 @@ def bench_serving(H, fac, r, lg, args):
     direct.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)
     dsat = direct.loadgen(sig, rate_hz=0, duration_s=secs, seed=2, **gen)
     direct.close()
-    log(f"serving: saturation {sat_hz:.4g} blocks/s; p99 by load " +
-        ", ".join(f"{k.split()[1]} {v['p99_ms'] * 1e3:.0f} us" + ("*" if v["generator_limited"] else "")
-                  for k, v in sweep.items()) +
-        f" (* generator-limited); real time p50/p99 {rt['p50_ms'] * 1e3:.0f}/{rt['p99_ms'] * 1e3:.0f} us")
+    log(f"serving ({gen['submit_threads']} submitting threads): saturation {sat_hz:.4g} blocks/s; p99 end-to-end / "
+        f"server by load " +
+        ", ".join(f"{k.split()[1]} {v['p99_ms'] * 1e3:.0f}/{v['p99_server_ms'] * 1e3:.0f} us" +
+                  ("*" if v["generator_limited"] else "") + ("+" if v["saturated"] else "") for k, v in sweep.items()) +
+        f" (* generator-limited, + saturated); real time p50/p99 {rt['p50_ms'] * 1e3:.0f}/{rt['p99_ms'] * 1e3:.0f} us")
     note(f"serving direct-launch saturation: {dsat['achieved_hz']:.4g} blocks/s")
     # the zero-copy ring: no copy commands per generation
     zc = H.Server(plan, n_streams, hbm_budget=1 << 30, flags=H.STREAM_ZERO_COPY)
@@ -322,6 +342,7 @@ def bench_serving(H, fac, r, lg, args):
             f"p99 {st['p99_ms'] * 1e3:.0f} us, batch {st['mean_batch']:.1f}")
     return {"workload": "1,024 streams at 48 kHz, blocks U{64..1024} samples, Poisson arrivals, K=16, "
                         "1,250 directions; arrival -> output in host memory",
+            "submit_threads": gen["submit_threads"],
             "saturation_blocks_per_s": sat_hz, "realtime_blocks_per_s": rt_hz,
             "saturation_x_realtime": sat_hz / rt_hz, "p50_ms_realtime": rt["p50_ms"], "p99_ms_realtime": rt["p99_ms"],
             "generations": info["generations"], "gen_samples": info["gen_samples"],
@@ -670,7 +691,9 @@ def headline(res: dict, detail_path=None) -> dict:
     sv = res.get("serving")
     if sv:
         s["serving"] = {"saturation_blocks_per_s": _r(sv["saturation_blocks_per_s"]),
-                        "realtime_p99_us": _r(sv["p99_ms_realtime"] * 1e3)}
+                        "realtime_p99_us": _r(sv["p99_ms_realtime"] * 1e3),
+                        "p99_us_by_load": {k.split()[1]: _r(v["p99_ms"] * 1e3, 3)
+                                           for k, v in (sv.get("load_sweep") or {}).items()}}
     sg = res.get("surrogate")
     if sg:
         ho = sg.get("heldout_E_dB_vs_factorization") or {}

@@ -220,6 +220,9 @@ typedef struct {
  *              in registers (needs lg <= 169).
  *              Default: the fused quad kernel, which keeps 4 shifted copies
  *              of the z tile in LDS so every tap read is 16 bytes per lane.
+ *              SPCONV_WG256: the quad kernel with 256-thread workgroups
+ *              instead of 512 (twice as many tiles resident per CU when LDS
+ *              allows; needs tile + lg + 2 <= 4096).
  *              All kernels sum every output in the same order, so results
  *              are bitwise identical across kernels and launch shapes.
  * The batch owns its device descriptor table (and z buffer when unfused).
@@ -231,6 +234,7 @@ typedef struct {
 #define SPCONV_UNFUSED 4
 #define SPCONV_LDS_GATHER 8
 #define SPCONV_REGWIN 16
+#define SPCONV_WG256 32
 
 typedef struct hrir_batch hrir_batch;
 
@@ -255,7 +259,8 @@ int spconv_batch_info(const hrir_batch* batch, int64_t* info5);
 void spconv_batch_destroy(hrir_batch* batch);
 
 /* Autotuner: for this job list, time every (tile, group, persistent) shape
- * the default kernel accepts (tile 1024..4096, group 0/4/8/16) with HIP
+ * the default kernel accepts (tile 1024..4096, group 0/4/8/16, workgroups of
+ * 512 or 256 threads) with HIP
  * events, 1 warm-up + 3 timed renders each on `stream`, and return the
  * fastest (tile, group, flags) and its ms per render.  force_flags
  * (SPCONV_PERSISTENT and/or SPCONV_LDS_GATHER, or 0) is part of every
@@ -449,7 +454,10 @@ void block_streams_destroy(hrir_streams* streams);
  *                everything; results not polled are dropped.  No other call
  *                on the server may run during or after it.
  * stream_submit, stream_end, stream_poll and stream_info may be called from
- * several threads at once.  Times are CLOCK_MONOTONIC nanoseconds: submit,
+ * several threads at once; submissions take no lock (a compare-and-swap on
+ * the open generation reserves a job slot and its samples).  The calls for
+ * one stream id must not overlap in time: a stream's blocks run in the
+ * order its (one) submitting thread made them.  Times are CLOCK_MONOTONIC nanoseconds: submit,
  * launch of the result's generation, and the moment the completion thread
  * saw its output in host memory.
  * ---------------------------------------------------------------------- */
@@ -595,10 +603,12 @@ void mlp_destroy(hrir_mlp* mlp);
  * process of rate_hz / T over its own streams.  A
  * polling thread collects the results; the call returns when all are in,
  * or with EDEVICE if none arrives for 30 s after submission ends.
- * A refused block is retried after a growing pause that leaves the server's
- * lock alone.  Latencies: arrival -> done (p50/p99/max), submit -> done
+ * A refused block is retried after a growing pause (retrying at once would
+ * hold up the threads that free room).  Latencies: arrival -> done (p50/p99/max), submit -> done
  * (p50/p99), and the two parts outside the server: arrival -> admitted and
- * done -> collected (p99/max).
+ * done -> collected (p99/max); arrival -> admitted splits into the
+ * generator's own lag (arrival -> first submit attempt) and the wait of
+ * refused blocks (back-pressure).
  * The server must not be polled by anyone else meanwhile.
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -612,7 +622,7 @@ typedef struct {
     int64_t max_blocks;
     const float* signal;     /* host f32[signal_len] */
     int64_t signal_len;
-    int32_t submit_threads;  /* submitting threads (0 or 1: one); thread t serves streams s % T == t */
+    int32_t submit_threads;  /* submitting threads (0 or 1: one); thread t serves the t-th of T contiguous stream ranges */
     int32_t pad;
 } stream_load;
 
@@ -633,6 +643,8 @@ typedef struct {
     double p99_collect_ms, max_collect_ms; /* done -> collected by the polling thread */
     double max_wait_ms;      /* longest submit -> launch of its generation */
     double max_launch_ms;    /* longest launch -> done of a generation */
+    double p99_gen_lag_ms, max_gen_lag_ms; /* arrival -> first offered to stream_submit: the generator's
+                                              own delay; large only when it cannot keep its schedule */
 } stream_load_stats;
 
 int stream_loadgen(hrir_server* server, const stream_load* cfg, stream_load_stats* stats);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libhrir.so")
 HRIR_OK, HRIR_EINVAL, HRIR_ENOMEM, HRIR_ENOTPD, HRIR_EAGAIN, HRIR_EDEVICE = 0, -1, -2, -3, -4, -5
 HRIR_REFIT_NNLS = 1
 HRIR_FACTORIZE_DEVICE = 2
-SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED, SPCONV_LDS_GATHER, SPCONV_REGWIN = 1, 2, 4, 8, 16
+SPCONV_PERSISTENT, SPCONV_GRAPH, SPCONV_UNFUSED, SPCONV_LDS_GATHER, SPCONV_REGWIN, SPCONV_WG256 = 1, 2, 4, 8, 16, 32
 
 _ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ENOTPD", -4: "EAGAIN", -5: "EDEVICE"}
 
@@ -81,7 +81,7 @@ class StreamLoadStats(ctypes.Structure):
                 ("p99_ms", c_double), ("max_ms", c_double), ("p50_server_ms", c_double),
                 ("p99_server_ms", c_double), ("p99_admit_ms", c_double), ("max_admit_ms", c_double),
                 ("p99_collect_ms", c_double), ("max_collect_ms", c_double), ("max_wait_ms", c_double),
-                ("max_launch_ms", c_double)]
+                ("max_launch_ms", c_double), ("p99_gen_lag_ms", c_double), ("max_gen_lag_ms", c_double)]
 
 
 def _preload_torch_fft():

@@ -1,5 +1,5 @@
 // Launch-shape autotuner for spconv batches: times candidate (tile length,
-// jobs per tile, persistent) shapes of one job list with HIP events and
+// jobs per tile, persistent, workgroup size) shapes of one job list with HIP events and
 // keeps the fastest, optionally cached in a JSON file keyed by the plan's
 // (K, lf, lg) and a coarse shape class of the job list.
 #include <hip/hip_runtime.h>
@@ -119,9 +119,11 @@ extern "C" int spconv_autotune(const hrir_plan* plan, const float* d_src, int64_
     const int groups[] = {0, 4, 8, 16};
     for (int tile : tiles)
         for (int group : groups)
-            for (int pers : {0, SPCONV_PERSISTENT}) {
+            for (int pers : {0, SPCONV_PERSISTENT})
+            for (int wg : {0, SPCONV_WG256}) {
                 if ((force_flags & SPCONV_PERSISTENT) && !pers) continue;
-                const int flags = force_flags | pers;
+                if (wg && (force_flags & SPCONV_LDS_GATHER)) continue;
+                const int flags = force_flags | pers | wg;
                 hrir_batch* b = nullptr;
                 if (spconv_batch_create(plan, src_off, src_len, n_src, jobs, n_jobs, tile, group, flags, &b)) continue;
                 float ms = 0.0f;

@@ -47,11 +47,24 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     if (rc) return rc;
     const int64_t launches0 = info[0], eagain0 = info[3];
     const int64_t cap = cfg->max_blocks;
-    std::vector<int64_t> arrival((size_t)cap), admit((size_t)cap, -1), lat, lat_srv, collect;
+    std::vector<int64_t> arrival((size_t)cap), admit((size_t)cap, -1), lag((size_t)cap, -1), lat, lat_srv, collect;
     lat.reserve((size_t)cap);
     lat_srv.reserve((size_t)cap);
     collect.reserve((size_t)cap);
-    std::atomic<int64_t> submitted{0};
+    // per submitting thread: its count of admitted blocks, on a cache line of
+    // its own (threads do not share a counter or a line of the arrival and
+    // admission arrays: thread t owns the tags [t * per, (t + 1) * per))
+    struct alignas(64) Count {
+        std::atomic<int64_t> n{0};
+    };
+    const int T = std::max(1, std::min(cfg->submit_threads > 0 ? cfg->submit_threads : 1, cfg->n_streams));
+    const int64_t per = cap / T;
+    std::vector<Count> sub_count((size_t)T);
+    auto submitted = [&] {
+        int64_t n = 0;
+        for (const Count& c : sub_count) n += c.n.load(std::memory_order_acquire);
+        return n;
+    };
     std::atomic<bool> submit_done{false};
     std::atomic<int64_t> give_up_ns{INT64_MAX};      // set once submission ends
     std::atomic<int> poll_error{0};
@@ -77,7 +90,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
                 t_last_done = std::max(t_last_done, r.t_done_ns);
             }
             n_done += n;
-            if (submit_done && n_done >= submitted) return;
+            if (submit_done && n_done >= submitted()) return;
             if (n == 0) {
                 if (now_ns() > give_up_ns) {          // results stopped coming: report, do not wait forever
                     poll_error = HRIR_EDEVICE;
@@ -88,9 +101,8 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
         }
     });
 
-    // T submitting threads, each a Poisson process of rate / T over the
-    // streams s with s % T == t; thread t uses the tags t, t + T, t + 2T, ...
-    const int T = std::max(1, std::min(cfg->submit_threads > 0 ? cfg->submit_threads : 1, cfg->n_streams));
+    // T submitting threads, each a Poisson process of rate / T over its own
+    // range of streams
     const bool open_loop = cfg->rate_hz > 0.0;
     const int64_t t0 = now_ns();
     const int64_t t_stop = t0 + (int64_t)(cfg->duration_s * 1e9);
@@ -98,7 +110,10 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     std::vector<int64_t> sent(T, 0);
     auto submitter = [&](int t) {
         std::mt19937_64 rng(cfg->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(t + 1));
-        const int my_streams = (cfg->n_streams - t + T - 1) / T;
+        // a contiguous range of streams per thread: neighbouring streams'
+        // per-stream state is then written by one thread only
+        const int s_begin = (int)((int64_t)cfg->n_streams * t / T);
+        const int my_streams = (int)((int64_t)cfg->n_streams * (t + 1) / T) - s_begin;
         std::uniform_int_distribution<int> len_d(cfg->block_min, cfg->block_max);
         std::uniform_int_distribution<int> sid_d(0, my_streams - 1);
         std::uniform_int_distribution<int> dir_d(0, cfg->n_filters / 2 - 1);
@@ -109,8 +124,8 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
         double t_next = (double)t0;
         int64_t j = 0;
         for (;;) {
-            const int64_t tag = j * T + t;
-            if (tag >= cap || poll_error != 0 || sub_error != 0) break;
+            const int64_t tag = t * per + j;
+            if (j >= per || poll_error != 0 || sub_error != 0) break;
             int64_t t_arr;
             if (open_loop) {
                 t_next += gap_d(rng) * 1e9;
@@ -123,17 +138,20 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
                 if (t_arr >= t_stop) break;
             }
             const int ls = sid_d(rng);
-            const int sid = ls * T + t;
+            const int sid = s_begin + ls;
             if ((rng() & 15) == 0) dir[(size_t)ls] = dir_d(rng);    // a direction change every ~16 blocks
             const int len = len_d(rng);
             const float* blk = cfg->signal + off_d(rng);
             arrival[(size_t)tag] = t_arr;
+            // how late the generator itself is: a block due at t_arr is first
+            // offered to the server only now
+            lag[(size_t)tag] = now_ns() - t_arr;
             int r;
             for (int tries = 0;; ++tries) {
                 r = stream_submit(srv, sid, blk, len, 2 * dir[(size_t)ls], 2 * dir[(size_t)ls] + 1, (uint64_t)tag);
                 if (r != HRIR_EAGAIN) break;
-                // back off without touching the server's lock: retrying at
-                // full speed would hold up the threads that free the room
+                // back off: retrying at full speed would hold up the
+                // threads that free the room
                 const int spins = 64 << std::min(tries, 5);
                 for (int i = 0; i < spins; ++i) __builtin_ia32_pause();
             }
@@ -143,7 +161,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
             }
             admit[(size_t)tag] = now_ns() - t_arr;
             ++j;
-            submitted.fetch_add(1);
+            sub_count[(size_t)t].n.store(j, std::memory_order_release);
         }
         sent[(size_t)t] = j;
     };
@@ -151,7 +169,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     for (int t = 1; t < T; ++t) subs.emplace_back(submitter, t);
     submitter(0);
     for (auto& th : subs) th.join();
-    const int64_t n = submitted.load();
+    const int64_t n = submitted();
     rc = sub_error.load();
     const int64_t t_sub_end = now_ns();
     give_up_ns = t_sub_end + 30000000000LL;
@@ -159,7 +177,7 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
     poller.join();
     if (rc) return fail(rc, "stream_loadgen: a submission failed");
     if (poll_error)
-        return fail(poll_error, "stream_loadgen: %s", poll_error == HRIR_EDEVICE && n_done < submitted
+        return fail(poll_error, "stream_loadgen: %s", poll_error == HRIR_EDEVICE && n_done < submitted()
                                                           ? "results stopped arriving for 30 s"
                                                           : "poll failed");
     rc = stream_info(srv, info);
@@ -186,6 +204,11 @@ extern "C" int stream_loadgen(hrir_server* srv, const stream_load* cfg, stream_l
         if (a >= 0) adm.push_back(a);
     st->p99_admit_ms = pct(adm, 0.99);
     st->max_admit_ms = pct(adm, 1.0);
+    adm.clear();
+    for (int64_t a : lag)
+        if (a >= 0) adm.push_back(a);
+    st->p99_gen_lag_ms = pct(adm, 0.99);
+    st->max_gen_lag_ms = pct(adm, 1.0);
     st->p99_collect_ms = pct(collect, 0.99);
     st->max_collect_ms = pct(collect, 1.0);
     st->max_wait_ms = (double)max_wait * 1e-6;

@@ -31,6 +31,7 @@
 
 #include "hrir_internal.h"
 #include "render_common.h"
+#include "render_quad.h"
 
 namespace hrir {
 
@@ -211,6 +212,7 @@ struct hrir_batch {
     const hrir_plan* plan = nullptr;
     int flags = 0, TB = 0, group = 0, grid = 0;
     int kind = 0;                             // KIND_* below
+    int nt = 512;                             // threads per workgroup of the quad kernel
     int64_t n_tiles = 0, n_jobs = 0;
     int64_t src_extent = 0, out_extent = 0;   // elements the job list touches
     size_t lds_bytes = 0;
@@ -287,9 +289,9 @@ int launch(hrir_batch* b, const float* d_src, float* d_out, hipStream_t st) {
         });
         if (rc) return rc;
     } else if (b->kind == KIND_QUAD) {
-        int rc = quad_launch(pl->lfp, pl->kp, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st, d_src,
-                             b->d_tiles, (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p, pl->d_g, d_out, pl->lg, b->TB,
-                             b->d_ctr);
+        int rc = quad_launch(pl->lfp, pl->kp, b->nt, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st,
+                             d_src, b->d_tiles, (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p, pl->d_g, d_out, pl->lg,
+                             b->TB, b->d_ctr);
         if (rc) return rc;
     } else if (b->kind == KIND_REGWIN) {
         int rc = rw_launch(pl->lfp, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st, d_src, b->d_tiles,
@@ -507,7 +509,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return fail(HRIR_EINVAL, "spconv_batch_create: null pointer");
     *out = nullptr;
     if (n_src < 0 || n_jobs < 0) return fail(HRIR_EINVAL, "spconv_batch_create: negative count");
-    if (flags & ~(SPCONV_PERSISTENT | SPCONV_GRAPH | SPCONV_UNFUSED | SPCONV_LDS_GATHER | SPCONV_REGWIN))
+    if (flags & ~(SPCONV_PERSISTENT | SPCONV_GRAPH | SPCONV_UNFUSED | SPCONV_LDS_GATHER | SPCONV_REGWIN | SPCONV_WG256))
         return fail(HRIR_EINVAL, "spconv_batch_create: unknown flags 0x%x", flags);
     const int kflags = flags & (SPCONV_UNFUSED | SPCONV_LDS_GATHER | SPCONV_REGWIN);
     if (kflags & (kflags - 1))
@@ -528,6 +530,11 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return fail(HRIR_EINVAL, "spconv_batch_create: tile=%d must be a multiple of %d in [%d, %d]", tile,
                     tile_unit, tile_unit, tile_max);
     if (group < 0) return fail(HRIR_EINVAL, "spconv_batch_create: group < 0");
+    if ((flags & SPCONV_WG256) && kind != KIND_QUAD)
+        return fail(HRIR_EINVAL, "spconv_batch_create: WG256 needs the default kernel");
+    if ((flags & SPCONV_WG256) && tile + plan->lg + 2 > kQSmallCover)
+        return fail(HRIR_EINVAL, "spconv_batch_create: WG256 needs tile + lg + 2 <= %d (tile %d, lg %d)", kQSmallCover,
+                    tile, plan->lg);
     if (plan->n_res > 1 && kind != KIND_QUAD)
         return fail(HRIR_EINVAL, "spconv_batch_create: a plan with %d resonance filters needs the default kernel",
                     plan->n_res);
@@ -536,6 +543,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     auto* b = new (std::nothrow) hrir_batch;
     if (!b) return fail(HRIR_ENOMEM, "spconv_batch_create: out of host memory");
     b->plan = plan; b->flags = flags; b->TB = tile; b->n_jobs = n_jobs; b->kind = kind;
+    b->nt = (flags & SPCONV_WG256) ? 256 : 512;
     for (int j = 0; j < n_jobs; ++j) {
         const int s = jobs[j].src;
         b->src_extent = std::max(b->src_extent, src_off[s] + src_len[s]);
@@ -604,8 +612,8 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
     // Kernel attributes and the persistent grid size.
     int rc = kind == KIND_REGWIN ? rw_prepare(plan->lfp, b->lds_bytes, (flags & SPCONV_PERSISTENT) != 0, b->n_tiles,
                                               &b->grid)
-             : kind == KIND_QUAD ? quad_prepare(plan->lfp, plan->kp, b->lds_bytes, (flags & SPCONV_PERSISTENT) != 0,
-                                                b->n_tiles, &b->grid)
+             : kind == KIND_QUAD ? quad_prepare(plan->lfp, plan->kp, b->nt, b->lds_bytes,
+                                                (flags & SPCONV_PERSISTENT) != 0, b->n_tiles, &b->grid)
                                  : dispatch(plan->lfp, plan->kp, [&](auto L, auto K) -> int {
         constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
         const void* kt = reinterpret_cast<const void*>(&k_render_tiles<LV, KV>);
@@ -773,7 +781,7 @@ extern "C" int spconv_render_noalloc(const hrir_plan* plan, const float* d_src, 
 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int grid = 0;
-    if (int rc = quad_prepare(plan->lfp, plan->kp, lds_bytes, false, nt, &grid)) return rc;
+    if (int rc = quad_prepare(plan->lfp, plan->kp, 512, lds_bytes, false, nt, &grid)) return rc;
     // the staging arrays and the device descriptors are reused by the next
     // call: whatever happens, wait for this one before the lock is released
     hipError_t e = hipMemcpyAsync(d_jobs, na_jobs, sizeof(JobDesc) * (size_t)n_jobs, hipMemcpyHostToDevice, st);
@@ -781,8 +789,8 @@ extern "C" int spconv_render_noalloc(const hrir_plan* plan, const float* d_src, 
         e = hipMemcpyAsync(d_tiles, na_tiles, sizeof(TileDesc) * (size_t)nt, hipMemcpyHostToDevice, st);
     int rc = HRIR_OK;
     if (e == hipSuccess) {
-        rc = quad_launch(plan->lfp, plan->kp, false, grid, lds_bytes, st, d_src, d_tiles, (int)nt, d_jobs, plan->d_r,
-                         plan->d_p, plan->d_g, d_out, lg, tile, nullptr);
+        rc = quad_launch(plan->lfp, plan->kp, 512, false, grid, lds_bytes, st, d_src, d_tiles, (int)nt, d_jobs,
+                         plan->d_r, plan->d_p, plan->d_g, d_out, lg, tile, nullptr);
         if (rc == HRIR_OK) e = hipGetLastError();
     }
     const hipError_t es = hipStreamSynchronize(st);

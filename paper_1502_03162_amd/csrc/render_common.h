@@ -162,10 +162,11 @@ int rw_launch(int lfp, bool persistent, int grid, size_t lds_bytes, hipStream_t 
 
 // Quad LDS-gather kernel (render_quad.hip), the default render path.
 int quad_lds_bytes(int TB, int lg, int lfp);
-int quad_prepare(int lfp, int kp, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid);
-int quad_launch(int lfp, int kp, bool persistent, int grid, size_t lds_bytes, hipStream_t st, const float* src,
-                const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r, const int* P,
-                const float* Gv, float* out, int lg, int TB, int* ctr);
+// nt: threads per workgroup, 512 or 256 (256 needs TB + lg + 2 <= 4096).
+int quad_prepare(int lfp, int kp, int nt, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid);
+int quad_launch(int lfp, int kp, int nt, bool persistent, int grid, size_t lds_bytes, hipStream_t st,
+                const float* src, const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r,
+                const int* P, const float* Gv, float* out, int lg, int TB, int* ctr);
 constexpr int kQuadTileMax = 4096;
 
 // Shape and device tables of a plan (render.hip owns the struct).

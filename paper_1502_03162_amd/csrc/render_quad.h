@@ -18,6 +18,7 @@ constexpr int kQWaves = kQThreads / 64;
 constexpr int kQPass = 2;             // FIR passes of 8 z values per thread (8192 z: tiles up to 4096)
 static_assert(kQChunk == 1024, "quad chunk");
 static_assert(kQPass * kQThreads * kZpt >= kQuadTileMax + 2048 + 3, "FIR passes cover the largest tile");
+constexpr int kQSmallCover = kQPass * 256 * kZpt;   // z values the FIR of a 256-thread workgroup covers
 static_assert(kZpt == 8, "the copy stores rotate 8 values per lane by lane / 8");
 
 // Floats per shifted copy: holds m < TB + H (+ padding so that the copies
@@ -49,10 +50,13 @@ struct NoHook {
 // prio (wave-uniform): raise the waves' issue priority while the source
 // window is loaded, so a new tile's loads go out ahead of other tiles'
 // gathers on the CU; it pays when the gather is long (many jobs per tile).
-template <int LFP, class Hook = NoHook>
+// NT: threads of the workgroup (512, or 256 when TB + lg + 2 <= 4096, so
+// that the two FIR passes of 8 z values per thread still cover the tile).
+template <int LFP, int NT = kQThreads, class Hook = NoHook>
 __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __restrict__ src,
                                            const float* __restrict__ r, int lg, int TB, float* lds, int tid,
                                            Hook&& after_source = Hook{}, bool prio = false) {
+    static_assert(NT == 512 || NT == 256, "quad workgroups have 256 or 512 threads");
     const int H = lg - 1;
     const int tile_len = min(TB, td.out_len - td.t0);
     const int NZ = tile_len + H + 3;           // z_win[u], u < NZ, covers every quad read
@@ -62,7 +66,7 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
     float* zc = lds;                           // the copies overwrite s_win after the FIR
 
     if (prio) __builtin_amdgcn_s_setprio(2);
-    stage_s<LFP, kQThreads>(td, src, H, nz8, s_win, tid);
+    stage_s<LFP, NT>(td, src, H, nz8, s_win, tid);
     after_source();
     if (prio) __builtin_amdgcn_s_setprio(0);
 
@@ -73,7 +77,7 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
     float zz[kQPass][kZpt];
 #pragma unroll
     for (int ps = 0; ps < kQPass; ++ps) {
-        const int u0 = (ps * kQThreads + tid) * kZpt;
+        const int u0 = (ps * NT + tid) * kZpt;
         if (u0 < nz8) {
             float w[LFP + kZpt];
 #pragma unroll
@@ -95,7 +99,7 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
     const int mlim = tile_len + H;
 #pragma unroll
     for (int ps = 0; ps < kQPass; ++ps) {
-        const int u0 = (ps * kQThreads + tid) * kZpt;
+        const int u0 = (ps * NT + tid) * kZpt;
         if (u0 >= 4 && u0 + kZpt <= mlim) {
             float* z0 = zc + u0;
             *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);

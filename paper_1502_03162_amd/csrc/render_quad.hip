@@ -36,12 +36,13 @@ namespace hrir {
 // priority (measured: 2-3 % faster at 40 jobs per tile, slower at 1..16).
 constexpr int kQPrioJobs = 24;
 
-template <int LFP, int KP>
+template <int LFP, int KP, int NT>
 __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float* __restrict__ src,
                                                  const JobDesc* __restrict__ jobs, const float* __restrict__ r,
                                                  const int* __restrict__ P, const float* __restrict__ Gv,
                                                  float* __restrict__ out, int lg, int TB, float* lds, int tid) {
-    quad_stage<LFP>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid, NoHook{}, td.job_count >= kQPrioJobs);
+    constexpr int kWv = NT / 64;
+    quad_stage<LFP, NT>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid, NoHook{}, td.job_count >= kQPrioJobs);
     const int H = lg - 1;
     const int CS = quad_cs(TB, H);
     const float* zc = lds;
@@ -111,8 +112,8 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
                     }
             }
     };
-    if (td.job_count >= kQWaves) {
-        for (int q = wave; q < td.job_count; q += kQWaves) {
+    if (td.job_count >= kWv) {
+        for (int q = wave; q < td.job_count; q += kWv) {
             const JobDesc jd = jobs[td.job_begin + q];
             load_taps(jd);
             // one chunk body in the loop: unrolling it doubles the hot code
@@ -121,7 +122,7 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
         }
     } else {
 #pragma unroll 1
-        for (int it = wave; it < td.job_count * nchunk; it += kQWaves) {
+        for (int it = wave; it < td.job_count * nchunk; it += kWv) {
             const int q = it / nchunk;
             const JobDesc jd = jobs[td.job_begin + q];
             load_taps(jd);
@@ -130,8 +131,10 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
     }
 }
 
-template <int LFP, int KP>
-__global__ __launch_bounds__(kQThreads, 4) void k_render_quad(const float* __restrict__ src,
+// 512-thread workgroups take 4 per CU (LDS at the default tile); 256-thread
+// ones are held to 64 VGPRs so that 8 fit (32 waves per CU).
+template <int LFP, int KP, int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 8) void k_render_quad(const float* __restrict__ src,
                                                                      const TileDesc* __restrict__ tiles,
                                                                      const JobDesc* __restrict__ jobs,
                                                                      const float* __restrict__ r,
@@ -140,15 +143,16 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_quad(const float* __res
                                                                      float* __restrict__ out, int lg, int TB) {
     extern __shared__ float4 smem4[];
     const TileDesc td = tiles[blockIdx.x];
-    render_tile_quad<LFP, KP>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4), (int)threadIdx.x);
+    render_tile_quad<LFP, KP, NT>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4),
+                                  (int)threadIdx.x);
 }
 
 // Persistent variant over the device tile counter (see k_render_persistent).
 // For lf <= 32 it is held to 64 VGPRs (8 waves per SIMD, 4 tiles per CU like
 // the one-tile kernel) at the cost of a few spilled dwords per lane; with
 // 73 VGPRs it would fit 3 tiles per CU, and the loop measured 2-5 % slower.
-template <int LFP, int KP>
-__global__ __launch_bounds__(kQThreads, LFP <= 32 ? 8 : 4) void k_render_quad_persistent(
+template <int LFP, int KP, int NT>
+__global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render_quad_persistent(
     const float* __restrict__ src, const TileDesc* __restrict__ tiles, int n_tiles,
     const JobDesc* __restrict__ jobs, const float* __restrict__ r, const int* __restrict__ P,
     const float* __restrict__ Gv, float* __restrict__ out, int lg, int TB, int* __restrict__ ctr) {
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kQThreads, LFP <= 32 ? 8 : 4) void k_render_quad_pe
         const int tid = (int)threadIdx.x + zero;
         const int z = __builtin_amdgcn_readfirstlane(zero);
         const TileDesc td = tiles[t];
-        render_tile_quad<LFP, KP>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
+        render_tile_quad<LFP, KP, NT>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
                                   reinterpret_cast<float*>(smem4), tid);
         __syncthreads();
     }
@@ -196,41 +200,52 @@ static int with_lf_k(int lfp, int kp, F&& f) {
     return fail(HRIR_EINVAL, "no quad kernel for lf pad %d, k pad %d", lfp, kp);
 }
 
-int quad_prepare(int lfp, int kp, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid) {
+template <class F>
+static int with_nt(int nt, F&& f) {
+    if (nt == 512) return f(std::integral_constant<int, 512>{});
+    if (nt == 256) return f(std::integral_constant<int, 256>{});
+    return fail(HRIR_EINVAL, "no quad kernel with %d threads", nt);
+}
+
+int quad_prepare(int lfp, int kp, int nt, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid) {
     return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
-        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
-        const void* kt = reinterpret_cast<const void*>(&k_render_quad<LV, KV>);
-        const void* kpers = reinterpret_cast<const void*>(&k_render_quad_persistent<LV, KV>);
-        hipError_t e = hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(kpers, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
-        if (!persistent) {
-            *grid = (int)n_tiles;
+        return with_nt(nt, [&](auto N) -> int {
+            constexpr int LV = decltype(L)::value, KV = decltype(K)::value, NV = decltype(N)::value;
+            const void* kt = reinterpret_cast<const void*>(&k_render_quad<LV, KV, NV>);
+            const void* kpers = reinterpret_cast<const void*>(&k_render_quad_persistent<LV, KV, NV>);
+            hipError_t e = hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(kpers, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
+            if (!persistent) {
+                *grid = (int)n_tiles;
+                return HRIR_OK;
+            }
+            int per_cu = 0, dev = 0, cus = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, NV, lds_bytes);
+            if (e == hipSuccess) e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
+            *grid = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, std::max<int64_t>(n_tiles, 1));
             return HRIR_OK;
-        }
-        int per_cu = 0, dev = 0, cus = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kpers, kQThreads, lds_bytes);
-        if (e == hipSuccess) e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
-        *grid = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, std::max<int64_t>(n_tiles, 1));
-        return HRIR_OK;
+        });
     });
 }
 
-int quad_launch(int lfp, int kp, bool persistent, int grid, size_t lds_bytes, hipStream_t st, const float* src,
-                const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r, const int* P,
-                const float* Gv, float* out, int lg, int TB, int* ctr) {
+int quad_launch(int lfp, int kp, int nt, bool persistent, int grid, size_t lds_bytes, hipStream_t st,
+                const float* src, const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r,
+                const int* P, const float* Gv, float* out, int lg, int TB, int* ctr) {
     return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
-        constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
-        if (persistent)
-            hipLaunchKernelGGL((k_render_quad_persistent<LV, KV>), dim3(grid), dim3(kQThreads), lds_bytes, st, src,
-                               tiles, n_tiles, jobs, r, P, Gv, out, lg, TB, ctr);
-        else
-            hipLaunchKernelGGL((k_render_quad<LV, KV>), dim3((unsigned)n_tiles), dim3(kQThreads), lds_bytes, st, src,
-                               tiles, jobs, r, P, Gv, out, lg, TB);
-        return HRIR_OK;
+        return with_nt(nt, [&](auto N) -> int {
+            constexpr int LV = decltype(L)::value, KV = decltype(K)::value, NV = decltype(N)::value;
+            if (persistent)
+                hipLaunchKernelGGL((k_render_quad_persistent<LV, KV, NV>), dim3(grid), dim3(NV), lds_bytes, st, src,
+                                   tiles, n_tiles, jobs, r, P, Gv, out, lg, TB, ctr);
+            else
+                hipLaunchKernelGGL((k_render_quad<LV, KV, NV>), dim3((unsigned)n_tiles), dim3(NV), lds_bytes, st,
+                                   src, tiles, jobs, r, P, Gv, out, lg, TB);
+            return HRIR_OK;
+        });
     });
 }
 

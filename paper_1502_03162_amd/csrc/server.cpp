@@ -20,13 +20,28 @@
 // kernel reads and writes in place: a generation is the wait and the launch.
 // A completion thread turns done events into results, handed out by
 // stream_poll.
+//
+// Admission takes no lock.  Each generation has one 64-bit reservation word
+// (closed bit, epoch, jobs, output samples); a submission claims a job slot
+// and its sample range with a compare-and-swap on it, fills them in, and
+// marks its slot ready.  The loop thread launches a generation by setting
+// its closed bit, which fixes its job count, and waits until that many slots
+// are ready.  Only opening a new generation, finished generations and
+// errors go through the server's mutex: the completion thread queues a
+// finished generation, not its results, and stream_poll reads the results
+// out of the generation's own tables.  A stream's
+// blocks keep their order because its next block only goes into a later
+// generation than its last one; submissions for one stream must therefore
+// not overlap in time (those of different streams may).
 #include <hip/hip_runtime.h>
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -50,12 +65,38 @@ int64_t now_ns() {
 
 enum GenState { kFree, kOpen, kLaunched, kDone, kHanded };
 
+// Reservation word of a generation: bit 63 closed, bits 53..62 epoch (the
+// generation's sequence number / ring size, mod 2^10, so that a submission
+// that read a stale sequence number cannot reserve in a recycled buffer),
+// bits 32..52 jobs, bits 0..31 output samples per ear.  A block's input sits
+// at the same offset as its output samples (flush jobs leave input unused).
+constexpr uint64_t kClosed = 1ull << 63;
+constexpr int kEpochShift = 53;
+constexpr uint64_t kEpochMask = 0x3ffull;
+constexpr int kJobShift = 32;
+constexpr uint64_t kJobMask = (1ull << 21) - 1;
+constexpr uint64_t kOutMask = (1ull << 32) - 1;
+
+inline uint64_t word_epoch(uint64_t w) { return (w >> kEpochShift) & kEpochMask; }
+inline int word_jobs(uint64_t w) { return (int)((w >> kJobShift) & kJobMask); }
+inline int64_t word_out(uint64_t w) { return (int64_t)(w & kOutMask); }
+
+// Per job slot, beside the job table: what the result reports, and `ready`
+// = generation sequence + 1 once the submission has filled the slot in.
+struct Slot {
+    uint64_t tag;
+    int64_t t_submit;
+    std::atomic<int64_t> ready{0};
+    int64_t pad;
+};
+
 struct Gen {
-    int64_t seq = -1;
-    GenState state = kFree;
-    int n_jobs = 0, max_m = 0, remaining = 0;
+    int64_t seq = -1;                      // set when opened, before the word is reset
+    std::atomic<uint64_t> word{kClosed};
+    GenState state = kFree;                // under the server mutex
+    int n_jobs = 0, max_m = 0;             // fixed at launch
     bool failed = false;                   // its launch failed: no results
-    int64_t in_used = 0, out_used = 0;     // input floats; output samples per ear
+    int64_t out_used = 0;                  // output samples per ear, fixed at launch
     int64_t t_launch = 0, t_done = 0;
     // pinned host: h_hdr[0] = job count, then the job table; inputs; outputs
     int32_t* h_hdr = nullptr;
@@ -70,8 +111,8 @@ struct Gen {
     hipEvent_t ev_kernel = nullptr, ev_done = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<uint64_t> tag;
-    std::vector<int64_t> t_submit;
+    std::unique_ptr<Slot[]> slot;          // per job slot
+    int next_result = 0;                   // results of this generation handed out so far
 };
 
 }  // namespace
@@ -84,27 +125,30 @@ struct hrir_server {
     int64_t cap_samples = 0;
     int tail = 0;
     hipStream_t st[2] = {nullptr, nullptr};
-    std::vector<Gen> gens;
-    std::vector<int64_t> last_seq;          // per stream: generation of its newest block
+    std::unique_ptr<Gen[]> gens;
+    std::vector<int64_t> last_seq;          // per stream: generation of its newest block (its submitter's)
 
-    std::mutex mu;
+    std::mutex mu;                          // opening generations, results, errors, thread hand-offs
     std::condition_variable cv_work;        // dispatcher: new jobs, a free device slot, close
     std::condition_variable cv_done;        // completer: a launch; pollers: results
-    int64_t head = 0;                       // oldest generation not yet free
-    int64_t tail_seq = 0;                   // one past the newest opened generation
-    int64_t next_launch = 0, next_done = 0;
+    std::atomic<int64_t> head{0};           // oldest generation not yet free
+    std::atomic<int64_t> tail_seq{0};       // one past the newest opened generation
+    std::atomic<int64_t> next_launch{0};
+    int64_t next_done = 0;
     int64_t enqueued = 0;                   // generations whose device work is fully enqueued
-    std::deque<hrir_result> results;
-    std::deque<int64_t> result_gen;         // generation of each queued result
-    bool closing = false, dispatcher_exited = false;
-    int err_code = 0;
+    std::deque<int64_t> done_gens;          // finished generations with results not yet all handed out
+    std::atomic<bool> closing{false};
+    bool dispatcher_exited = false;
+    std::atomic<int> err_code{0};
     std::string err_msg;
     // statistics
-    int64_t n_launches = 0, n_results = 0, n_samples = 0, n_eagain = 0, max_batch = 0;
+    int64_t n_launches = 0, n_results = 0, n_samples = 0, max_batch = 0;
+    std::atomic<int64_t> n_eagain{0};
 
     std::thread dispatcher, completer;
 
     Gen& gen(int64_t seq) { return gens[(size_t)(seq % n_gens)]; }
+    uint64_t epoch(int64_t seq) const { return (uint64_t)(seq / n_gens) & kEpochMask; }
 };
 
 namespace {
@@ -112,8 +156,8 @@ namespace {
 void set_error(hrir_server* s, const char* where, hipError_t e) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->err_code) {
-        s->err_code = HRIR_EDEVICE;
         s->err_msg = std::string(where) + ": " + hipGetErrorString(e);
+        s->err_code = HRIR_EDEVICE;
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
@@ -126,25 +170,26 @@ void open_gen(hrir_server* s, int64_t seq) {
     g.state = kOpen;
     g.n_jobs = 0;
     g.max_m = 0;
-    g.in_used = 0;
     g.out_used = 0;
-    g.remaining = 0;
     g.failed = false;
-    g.tag.clear();
-    g.t_submit.clear();
+    g.next_result = 0;
+    g.word.store(s->epoch(seq) << kEpochShift, std::memory_order_release);
 }
 
 // Releases generations whose results have all been handed out, in order.
+// Lock held.
 void release_handed(hrir_server* s) {
-    while (s->head < s->tail_seq && s->gen(s->head).state == kHanded) {
-        s->gen(s->head).state = kFree;
-        ++s->head;
+    int64_t h = s->head.load(std::memory_order_relaxed);
+    while (h < s->tail_seq.load(std::memory_order_relaxed) && s->gen(h).state == kHanded) {
+        s->gen(h).state = kFree;
+        ++h;
     }
+    s->head.store(h, std::memory_order_release);
 }
 
 // Takes the server lock for a short critical section: spin on try_lock for
-// about a microsecond before blocking, so that submitting threads that
-// meet at the lock hand it over without sleeping in the kernel.
+// about a microsecond before blocking, so that threads that meet at the lock
+// hand it over without sleeping in the kernel.
 std::unique_lock<std::mutex> lock_short(std::mutex& mu) {
     for (int i = 0; i < 64; ++i) {
         if (mu.try_lock()) return std::unique_lock<std::mutex>(mu, std::adopt_lock);
@@ -153,20 +198,22 @@ std::unique_lock<std::mutex> lock_short(std::mutex& mu) {
     return std::unique_lock<std::mutex>(mu);
 }
 
-// Places one job (block or flush) for `stream` in the oldest generation that
-// can take it.  Lock held.  Returns the generation or -1 (no room: EAGAIN).
-int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
-    int64_t q = std::max(s->next_launch, s->last_seq[stream] + 1);
-    for (;; ++q) {
-        if (q >= s->head + s->n_gens) return -1;
-        if (q == s->tail_seq) {
-            if (s->gen(q).state != kFree) return -1;
-            open_gen(s, q);
-            ++s->tail_seq;
+// Reserves a job slot and m output samples in generation q; returns the
+// word before the reservation, or 0 with *ok false when q cannot take it
+// (closed, recycled, or full).
+uint64_t reserve(hrir_server* s, Gen& g, int64_t q, int m, bool* ok) {
+    const uint64_t ep = s->epoch(q);
+    uint64_t w = g.word.load(std::memory_order_acquire);
+    for (;;) {
+        if ((w & kClosed) || word_epoch(w) != ep || word_jobs(w) >= s->cap_jobs || word_out(w) + m > s->cap_samples) {
+            *ok = false;
+            return 0;
         }
-        Gen& g = s->gen(q);
-        if (g.n_jobs < s->cap_jobs && g.in_used + n_in <= s->cap_samples && g.out_used + m <= s->cap_samples)
-            return q;
+        const uint64_t nw = w + (1ull << kJobShift) + (uint64_t)m;
+        if (g.word.compare_exchange_weak(w, nw, std::memory_order_acq_rel, std::memory_order_acquire)) {
+            *ok = true;
+            return w;
+        }
     }
 }
 
@@ -175,38 +222,60 @@ int64_t place(hrir_server* s, int32_t stream, int m, int64_t n_in) {
 // Every other change that can make it launchable notifies on its own (a
 // completion frees a slot; close; an error), so a submission that does not
 // complete this condition wakes nobody: the loop thread is not woken once
-// per block.  Lock held.
+// per block.  The mutex orders the notification against the loop thread's
+// check of its wait condition.
 void wake_dispatcher(hrir_server* s, int64_t q) {
-    if (q == s->next_launch && s->gen(q).n_jobs > 0 && s->next_launch - s->next_done < kDepth)
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (q == s->next_launch.load(std::memory_order_relaxed) && s->next_launch - s->next_done < kDepth)
         s->cv_work.notify_one();
 }
 
 int enqueue_job(hrir_server* s, int32_t stream, const float* block, int32_t n, int32_t filt_l, int32_t filt_r,
                 uint64_t tag, bool end, const char* fn) {
     const int m = end ? s->tail : n;
-    const int64_t n_in = end ? 0 : n;
-    auto lk = lock_short(s->mu);
-    if (s->err_code) return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
-    if (s->closing) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
-    const int64_t q = place(s, stream, m, n_in);
-    if (q < 0) {
-        ++s->n_eagain;
-        return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+    if (s->err_code.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        return fail(s->err_code, "%s: %s", fn, s->err_msg.c_str());
     }
-    Gen& g = s->gen(q);
-    const int i = g.n_jobs++;
-    const int64_t in_off = g.in_used;
-    g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, in_off,
-                       2 * g.out_used};
-    if (n_in) std::memcpy(g.h_in + in_off, block, sizeof(float) * (size_t)n_in);
-    g.in_used += n_in;
-    g.out_used += m;
-    g.max_m = std::max(g.max_m, m);
-    g.tag.push_back(tag);
-    g.t_submit.push_back(now_ns());
-    s->last_seq[stream] = q;
-    if (i == 0) wake_dispatcher(s, q);
-    return HRIR_OK;
+    if (s->closing.load(std::memory_order_acquire)) return fail(HRIR_EINVAL, "%s: the server is closing", fn);
+    // the oldest generation after this stream's last block that can take it
+    int64_t q = std::max(s->next_launch.load(std::memory_order_acquire), s->last_seq[stream] + 1);
+    for (;; ++q) {
+        if (q >= s->head.load(std::memory_order_acquire) + s->n_gens) {
+            s->n_eagain.fetch_add(1, std::memory_order_relaxed);
+            return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+        }
+        if (q >= s->tail_seq.load(std::memory_order_acquire)) {
+            // q is the next generation to open (q never passes tail_seq:
+            // next_launch and every stream's last generation are below it)
+            auto lk = lock_short(s->mu);
+            const int64_t ts = s->tail_seq.load(std::memory_order_relaxed);
+            if (q >= ts) {
+                if (q != ts || q >= s->head.load(std::memory_order_relaxed) + s->n_gens || s->gen(q).state != kFree) {
+                    s->n_eagain.fetch_add(1, std::memory_order_relaxed);
+                    return fail(HRIR_EAGAIN, "%s: no generation buffer has room (poll to release results)", fn);
+                }
+                open_gen(s, q);
+                s->tail_seq.store(q + 1, std::memory_order_release);
+            }
+        }
+        Gen& g = s->gen(q);
+        bool ok = false;
+        const uint64_t w = reserve(s, g, q, m, &ok);
+        if (!ok) continue;
+        // the slot is ours: fill it in, then mark it ready
+        const int i = word_jobs(w);
+        const int64_t off = word_out(w);
+        g.h_jobs[i] = BJob{stream, end ? 0 : n, filt_l, filt_r, end ? (kJobFlush | kJobReset) : 0, 0, off, 2 * off};
+        if (!end) std::memcpy(g.h_in + off, block, sizeof(float) * (size_t)n);
+        Slot& sl = g.slot[(size_t)i];
+        sl.tag = tag;
+        sl.t_submit = now_ns();
+        s->last_seq[stream] = g.seq;        // stable: g cannot launch before its slot is ready
+        sl.ready.store(g.seq + 1, std::memory_order_release);
+        if (i == 0) wake_dispatcher(s, g.seq);
+        return HRIR_OK;
+    }
 }
 
 // Enqueues generation g on HIP stream `st`; `prev` is the previous
@@ -216,8 +285,8 @@ hipError_t launch_gen(hrir_server* s, Gen& g, hipStream_t st, hipEvent_t prev) {
     const bool zc = (s->flags & STREAM_ZERO_COPY) != 0;     // the kernel reads the host tables in place
     hipError_t e = hipSuccess;
     if (!zc) e = hipMemcpyAsync(g.d_hdr, g.h_hdr, 64 + sizeof(BJob) * (size_t)g.n_jobs, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && g.in_used && !zc)
-        e = hipMemcpyAsync(g.d_in, g.h_in, sizeof(float) * (size_t)g.in_used, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g.out_used && !zc)      // inputs sit at their jobs' output offsets
+        e = hipMemcpyAsync(g.d_in, g.h_in, sizeof(float) * (size_t)g.out_used, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && prev) e = hipStreamWaitEvent(st, prev, 0);
     if (e == hipSuccess) {
         if (g.exec)
@@ -235,27 +304,49 @@ hipError_t launch_gen(hrir_server* s, Gen& g, hipStream_t st, hipEvent_t prev) {
 void dispatcher_main(hrir_server* s) {
     (void)hipSetDevice(s->sh.device);
     hipEvent_t prev = nullptr;
+    // a generation has jobs once a submission has reserved a slot in it
+    auto has_jobs = [&](int64_t q) {
+        return q < s->tail_seq.load(std::memory_order_acquire) &&
+               word_jobs(s->gen(q).word.load(std::memory_order_acquire)) > 0;
+    };
     for (;;) {
         std::unique_lock<std::mutex> lk(s->mu);
         s->cv_work.wait(lk, [&] {
             if (s->err_code) return true;
-            const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
+            const bool ready = has_jobs(s->next_launch);
             if (s->closing && !ready) return true;
             return ready && s->next_launch - s->next_done < kDepth;
         });
-        const bool ready = s->next_launch < s->tail_seq && s->gen(s->next_launch).n_jobs > 0;
+        const bool ready = has_jobs(s->next_launch);
         if (s->err_code || (s->closing && !ready)) {
             s->dispatcher_exited = true;
             s->cv_done.notify_all();
             return;
         }
-        const int64_t seq = s->next_launch++;
+        const int64_t seq = s->next_launch.load(std::memory_order_relaxed);
         Gen& g = s->gen(seq);
+        // close the generation: no reservation succeeds after this, so its
+        // job count is fixed; later submissions go to the next generations
+        const uint64_t w = g.word.fetch_or(kClosed, std::memory_order_acq_rel);
+        s->next_launch.store(seq + 1, std::memory_order_release);
         g.state = kLaunched;
-        g.t_launch = now_ns();
         s->n_launches++;
-        s->max_batch = std::max<int64_t>(s->max_batch, g.n_jobs);
         lk.unlock();
+        // wait for the submissions that hold a slot to finish filling it in
+        const int n_jobs = word_jobs(w);
+        for (int i = 0; i < n_jobs; ++i)
+            for (int spins = 0; g.slot[(size_t)i].ready.load(std::memory_order_acquire) != seq + 1; ++spins) {
+                if (spins < 256)
+                    __builtin_ia32_pause();
+                else
+                    std::this_thread::yield();
+            }
+        g.n_jobs = n_jobs;
+        g.out_used = word_out(w);
+        int max_m = 0;
+        for (int i = 0; i < n_jobs; ++i) max_m = std::max(max_m, block_job_len(s->sh, g.h_jobs[i]));
+        g.max_m = max_m;
+        g.t_launch = now_ns();
         // the generation no longer takes submissions: its tables are stable
         const hipError_t e = launch_gen(s, g, s->st[seq & 1], prev);
         prev = g.ev_kernel;
@@ -271,6 +362,7 @@ void dispatcher_main(hrir_server* s) {
         // only now is the done event recorded for this generation: before
         // this, querying it would see an earlier use of the buffer
         lk.lock();
+        s->max_batch = std::max<int64_t>(s->max_batch, g.n_jobs);
         s->enqueued = seq + 1;
         s->cv_done.notify_all();
     }
@@ -302,26 +394,15 @@ void completer_main(hrir_server* s) {
         }
         lk.lock();
         g.t_done = t_done;
-        g.state = kDone;
-        g.remaining = failed ? 0 : g.n_jobs;
-        if (failed) g.state = kHanded;
-        for (int i = 0; i < g.remaining; ++i) {
-            const BJob& j = g.h_jobs[i];
-            const int m = block_job_len(s->sh, j);
-            hrir_result r{};
-            r.tag = g.tag[i];
-            r.stream_id = j.slot;
-            r.n = m;
-            r.out = g.h_out + j.out_off;
-            r.t_submit_ns = g.t_submit[i];
-            r.t_launch_ns = g.t_launch;
-            r.t_done_ns = t_done;
-            r.flags = (j.flags & kJobFlush) ? STREAM_RESULT_TAIL : 0;
-            s->results.push_back(r);
-            s->result_gen.push_back(seq);
-            s->n_samples += m;
+        g.next_result = 0;
+        if (failed) {
+            g.state = kHanded;
+        } else {
+            g.state = kDone;
+            s->done_gens.push_back(seq);
+            s->n_results += g.n_jobs;
+            s->n_samples += g.out_used;
         }
-        s->n_results += g.remaining;
         ++s->next_done;
         s->cv_done.notify_all();
         s->cv_work.notify_all();
@@ -329,7 +410,8 @@ void completer_main(hrir_server* s) {
 }
 
 void free_server(hrir_server* s) {
-    for (Gen& g : s->gens) {
+    for (int gi = 0; s->gens && gi < s->n_gens; ++gi) {
+        Gen& g = s->gens[(size_t)gi];
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.graph) (void)hipGraphDestroy(g.graph);
         if (g.ev_kernel) (void)hipEventDestroy(g.ev_kernel);
@@ -398,11 +480,16 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
 
     s->flags = flags;
     s->cap_jobs = max_streams;
-    s->cap_samples = cap;
+    s->cap_samples = std::min<int64_t>(cap, (int64_t)kOutMask);   // the reservation word's sample field
     s->n_gens = (int)n_gens;
     s->tail = tail;
     s->last_seq.assign(max_streams, -1);
-    s->gens.resize(s->n_gens);
+    s->gens.reset(new (std::nothrow) Gen[(size_t)s->n_gens]);
+    if (!s->gens) {
+        s->n_gens = 0;
+        free_server(s);
+        return fail(HRIR_ENOMEM, "stream_open: out of host memory");
+    }
     hipError_t e = hipSuccess;
     for (hipStream_t& x : s->st)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
@@ -411,7 +498,10 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
     const bool zc = (flags & STREAM_ZERO_COPY) != 0;
     const unsigned host_flags = zc ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
     auto device_view = [](void* h, void** d) { return hipHostGetDevicePointer(d, h, 0); };
-    for (Gen& g : s->gens) {
+    for (int gi = 0; gi < s->n_gens; ++gi) {
+        Gen& g = s->gens[(size_t)gi];
+        g.slot.reset(new (std::nothrow) Slot[(size_t)s->cap_jobs]);
+        if (!g.slot) e = hipErrorOutOfMemory;
         if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_hdr, hdr_bytes, host_flags);
         if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_in, sizeof(float) * (size_t)cap, host_flags);
         if (e == hipSuccess) e = hipHostMalloc((void**)&g.h_out, sizeof(float) * 2 * (size_t)cap, host_flags);
@@ -484,20 +574,35 @@ extern "C" int stream_poll(hrir_server* s, hrir_result* out, int32_t max, int32_
     // results handed out by the previous poll are no longer referenced
     release_handed(s);
     // wake on results or an error; never wait when nothing is queued or running
-    auto pending = [&] { return !s->results.empty() || s->err_code || s->next_done == s->tail_seq; };
+    auto pending = [&] { return !s->done_gens.empty() || s->err_code || s->next_done == s->tail_seq; };
     if (timeout_us < 0)
         s->cv_done.wait(lk, pending);
     else if (timeout_us > 0)
         s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), pending);
-    if (s->results.empty() && s->err_code) return fail(s->err_code, "stream_poll: %s", s->err_msg.c_str());
+    if (s->done_gens.empty() && s->err_code) return fail(s->err_code, "stream_poll: %s", s->err_msg.c_str());
     int n = 0;
-    while (n < max && !s->results.empty()) {
-        out[n++] = s->results.front();
-        const int64_t seq = s->result_gen.front();
-        s->results.pop_front();
-        s->result_gen.pop_front();
-        Gen& g = s->gen(seq);
-        if (--g.remaining == 0) g.state = kHanded;
+    while (n < max && !s->done_gens.empty()) {
+        Gen& g = s->gen(s->done_gens.front());
+        const int take = std::min(max - n, g.n_jobs - g.next_result);
+        for (int i = g.next_result; i < g.next_result + take; ++i) {
+            const BJob& j = g.h_jobs[i];
+            const Slot& sl = g.slot[(size_t)i];
+            hrir_result& r = out[n++];
+            r = hrir_result{};
+            r.tag = sl.tag;
+            r.stream_id = j.slot;
+            r.n = block_job_len(s->sh, j);
+            r.out = g.h_out + j.out_off;
+            r.t_submit_ns = sl.t_submit;
+            r.t_launch_ns = g.t_launch;
+            r.t_done_ns = g.t_done;
+            r.flags = (j.flags & kJobFlush) ? STREAM_RESULT_TAIL : 0;
+        }
+        g.next_result += take;
+        if (g.next_result == g.n_jobs) {
+            g.state = kHanded;              // freed by the next poll: the results point into it
+            s->done_gens.pop_front();
+        }
     }
     return n;
 }
@@ -508,11 +613,11 @@ extern "C" int stream_info(const hrir_server* s, int64_t* info8) {
     auto* m = const_cast<hrir_server*>(s);
     std::lock_guard<std::mutex> lk(m->mu);
     int64_t queued = 0;
-    for (int64_t q = s->next_launch; q < s->tail_seq; ++q) queued += m->gen(q).n_jobs;
+    for (int64_t q = s->next_launch; q < s->tail_seq; ++q) queued += word_jobs(m->gen(q).word.load());
     info8[0] = s->n_launches;
     info8[1] = s->n_results;
     info8[2] = s->n_samples;
-    info8[3] = s->n_eagain;
+    info8[3] = s->n_eagain.load();
     info8[4] = s->max_batch;
     info8[5] = s->n_gens;
     info8[6] = s->cap_samples;
@@ -524,7 +629,7 @@ extern "C" void stream_close(hrir_server* s) {
     if (!s) return;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        s->closing = true;
+        s->closing.store(true, std::memory_order_release);
     }
     s->cv_work.notify_all();
     s->cv_done.notify_all();

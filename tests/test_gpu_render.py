@@ -77,7 +77,7 @@ def test_config0_end_to_end(dev):
     print(f"config0 worst rel L2 {worst:.3e}", flush=True)
 
 
-@pytest.mark.parametrize("kernel", ["quad", "lds_gather", "regwin"])
+@pytest.mark.parametrize("kernel", ["quad", "quad256", "lds_gather", "regwin"])
 @pytest.mark.parametrize("lf,lg,k", [(32, 169, 16), (1, 1, 1), (5, 2, 2), (17, 40, 3), (33, 300, 32),
                                      (64, 2048, 64), (16, 169, 8), (32, 169, 64), (64, 169, 33)])
 def test_ragged_lengths_and_shapes(dev, lf, lg, k, kernel):
@@ -96,8 +96,12 @@ def test_ragged_lengths_and_shapes(dev, lf, lg, k, kernel):
     if kernel == "regwin" and lg > 169:
         pytest.skip("the register-window kernel serves lg <= 169")
     plan = h.Plan(r, p, g, lg)
-    flags = {"quad": 0, "lds_gather": h.SPCONV_LDS_GATHER, "regwin": h.SPCONV_REGWIN}[kernel]
-    rows = render_rows(plan, srcs, jobs, dev, flags=flags)
+    flags = {"quad": 0, "quad256": h.SPCONV_WG256, "lds_gather": h.SPCONV_LDS_GATHER,
+             "regwin": h.SPCONV_REGWIN}[kernel]
+    # 256-thread workgroups cover tile + lg + 2 <= 4096 z values: at lg = 2048
+    # the largest tile they take is 1024
+    tile = 1024 if kernel == "quad256" and lg > 2048 - 2 else 0
+    rows = render_rows(plan, srcs, jobs, dev, flags=flags, tile=tile)
     check(rows, oracle_rows(r, srcs, p, g, lg, jobs))
 
 
@@ -141,9 +145,11 @@ def test_launch_variants_bitwise_identical(dev):
     plan, r, p, g, lg, srcs, jobs = _variant_setup()
     base = render_rows(plan, srcs, jobs, dev)
     check(base, oracle_rows(r, srcs, p, g, lg, jobs))
-    L, R, PS = h.SPCONV_LDS_GATHER, h.SPCONV_REGWIN, h.SPCONV_PERSISTENT
+    L, R, PS, W = h.SPCONV_LDS_GATHER, h.SPCONV_REGWIN, h.SPCONV_PERSISTENT, h.SPCONV_WG256
     variants = [dict(tile=1024), dict(tile=2048), dict(tile=3072), dict(group=1), dict(group=3),
                 dict(flags=PS), dict(flags=PS, tile=2048, reps=3),
+                dict(flags=W), dict(flags=W, tile=1024), dict(flags=W, tile=3072), dict(flags=W, group=3),
+                dict(flags=W | PS, reps=3), dict(flags=W | PS, tile=1024, reps=3),
                 dict(flags=L), dict(flags=L, tile=1024), dict(flags=L, tile=8192), dict(flags=L, tile=16384),
                 dict(flags=L, group=3), dict(flags=L | PS), dict(flags=L | PS, tile=2048, reps=3),
                 dict(flags=R), dict(flags=R, tile=12288), dict(flags=R, group=3), dict(flags=R | PS, reps=3),
@@ -164,7 +170,8 @@ def test_graph_replays_match_eager(dev):
     src = torch.from_numpy(np.concatenate(srcs)).to(dev)
     out_off, total = h.row_layout(plan, lens, jobs)
     for flags in (h.SPCONV_GRAPH, h.SPCONV_GRAPH | h.SPCONV_PERSISTENT, h.SPCONV_GRAPH | h.SPCONV_LDS_GATHER,
-                  h.SPCONV_GRAPH | h.SPCONV_REGWIN | h.SPCONV_PERSISTENT):
+                  h.SPCONV_GRAPH | h.SPCONV_REGWIN | h.SPCONV_PERSISTENT,
+                  h.SPCONV_GRAPH | h.SPCONV_WG256 | h.SPCONV_PERSISTENT):
         out = torch.zeros(total, dtype=torch.float32, device=dev)
         b = h.Batch(plan, off, lens, [(s, f, o) for (s, f), o in zip(jobs, out_off)], flags=flags)
         for rep in range(4):
