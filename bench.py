@@ -380,24 +380,42 @@ def filter_scores(X, f, p, g, lg) -> dict:
             "nnze_mean": float(np.mean(np.count_nonzero(G, axis=1)))}
 
 
-def fine_tune(H, X, f, lg, k, fac) -> dict:
+def fine_tune(H, X, f, lg, k, fac, host_reference=False) -> dict:
     """Alg. 1's last step with f fixed, at a budget of k taps per filter:
     top-k of G with the NNLS refit on that support (the library's default),
     and the paper's own sparsifier, the L1-NNLS of Eq. (14) with lambda
     searched per filter for at most k taps, with the identity transform and
     with the window transform of Eq. (16), its bandwidth tuned per HRIR at
-    that sparsity."""
+    that sparsity.  The L1-NNLS solves run on the GPU; with host_reference
+    the host path runs too, for its time and to check the two tap tables."""
     res = {"topk_refit": filter_scores(X, f, fac["p"], fac["g"], lg)}
-    t = time.perf_counter()
-    r = H.sparsify(X, f, k, "I", target_nnze=k)
-    res["l1_nnls_identity"] = dict(filter_scores(X, f, r["p"], r["g"], lg), host_s=time.perf_counter() - t)
-    t = time.perf_counter()
     grid_k = [15.0, 23.0, 35.0, 53.0, 80.0, float("inf")]
-    sig_k, _ = H.tune_sigma(X, f, grid_k, target_nnze=k)
-    r = H.sparsify(X, f, k, "W", sigma=sig_k, target_nnze=k)
+
+    def run(device):
+        t = time.perf_counter()
+        ri = H.sparsify(X, f, k, "I", target_nnze=k, device=device)
+        t_i = time.perf_counter() - t
+        t = time.perf_counter()
+        sig_k, _ = H.tune_sigma(X, f, grid_k, target_nnze=k, device=device)
+        rw = H.sparsify(X, f, k, "W", sigma=sig_k, target_nnze=k, device=device)
+        return ri, t_i, sig_k, rw, time.perf_counter() - t
+
+    ri, t_i, sig_k, rw, t_w = run(True)
+    res["l1_nnls_identity"] = dict(filter_scores(X, f, ri["p"], ri["g"], lg), device_s=t_i)
     res[f"l1_nnls_window_sigma_tuned_at_{k}_taps"] = dict(
-        filter_scores(X, f, r["p"], r["g"], lg), sigma_grid=grid_k, sigma_median=float(np.median(sig_k)),
-        frac_identity=float(np.mean(np.isinf(sig_k))), host_s=time.perf_counter() - t)
+        filter_scores(X, f, rw["p"], rw["g"], lg), sigma_grid=grid_k, sigma_median=float(np.median(sig_k)),
+        frac_identity=float(np.mean(np.isinf(sig_k))), device_s=t_w,
+        solves=int(X.shape[0] * (len(grid_k) + 1)))
+    if host_reference:
+        hi, h_i, hsig, hw, h_w = run(False)
+        same = (np.array_equal(hi["p"], ri["p"]) and np.array_equal(hw["p"], rw["p"]) and
+                np.array_equal(hsig, sig_k) and np.allclose(hi["g"], ri["g"], rtol=1e-6, atol=0) and
+                np.allclose(hw["g"], rw["g"], rtol=1e-6, atol=0))
+        res["l1_nnls_identity"]["host_s"] = h_i
+        res[f"l1_nnls_window_sigma_tuned_at_{k}_taps"]["host_s"] = h_w
+        res["device_equals_host"] = bool(same)
+        log(f"L1-NNLS on the GPU: identity {t_i:.2f} s (host {h_i:.2f} s), window tuned at {k} taps {t_w:.2f} s "
+            f"(host {h_w:.2f} s); tap tables equal to the host's: {same}")
     return res
 
 
@@ -419,19 +437,21 @@ def bench_quality(H, hs, fac, lf, lg, k, fact_iters, paper_iters):
         t = time.perf_counter()
         pipes[f"alg1_lambda0_T{T}"] = H.factorize(X, lf, T, k, seed=7, lambda0=0.0, want_cost=False, device=True)
         note(f"Alg. 1 at lambda = 0, T = {T}: factorized in {time.perf_counter() - t:.2f} s")
-    for name, fc in pipes.items():
-        res = fine_tune(H, X, fc["f"], lg, k, fc)
+    for pi, (name, fc) in enumerate(pipes.items()):
+        res = fine_tune(H, X, fc["f"], lg, k, fc, host_reference=(pi == 0))
         out[name] = res
         for v, q in res.items():
+            if not isinstance(q, dict):
+                continue
             note(f"quality {name} / {v}: E_dB {q['E_dB']:.2f} (worst filter {q['E_dB_worst_filter']:.2f}, "
                  f"{100 * q['frac_filters_above_-30dB']:.1f} % above -30 dB), SD {q['SD_dB_mean']:.3f} dB, "
                  f"NNZE {q['nnze_mean']:.2f}")
         log(f"quality {name}: E_dB " + ", ".join(f"{v} {q['E_dB']:.1f} (worst {q['E_dB_worst_filter']:.1f})"
-                                                 for v, q in res.items()))
+                                                 for v, q in res.items() if isinstance(q, dict)))
     f = fac["f"]
     grid = [15.0 + 2.0 * i for i in range(25)] + [100.0, 160.0, 250.0, float("inf")]
-    _, sd_tuned = H.tune_sigma(X, f, grid)
-    _, sd_id = H.tune_sigma(X, f, [float("inf")])
+    _, sd_tuned = H.tune_sigma(X, f, grid, device=True)
+    _, sd_id = H.tune_sigma(X, f, [float("inf")], device=True)
     out["sigma_table_lambda0"] = {"identity_SD_dB_mean": float(np.mean(sd_id)),
                                   "tuned_SD_dB_mean": float(np.mean(sd_tuned)),
                                   "relative_drop": float(1 - np.mean(sd_tuned) / np.mean(sd_id))}

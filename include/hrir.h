@@ -144,6 +144,23 @@ int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int3
                     int32_t n_grid, double lambda, int32_t target_nnze, double threshold, double* sigma_out,
                     double* sd_out);
 
+/* The same two calls with the L1-NNLS solves (Eq. (14), and the lambda
+ * search) on the current GPU in FP64: the host forms the normal matrices and
+ * right-hand sides, one wavefront per (row, bandwidth) problem runs the
+ * host's active-set steps and bisection in the host's order, and the host
+ * finishes (tap tables, errors, spectral distortion).  Same arguments,
+ * outputs and errors as the host calls (the device path needs
+ * m - lf + 1 <= 256; EINVAL otherwise, EDEVICE / ENOMEM on device
+ * failures); inputs and outputs are host memory and the calls return when
+ * everything is done. */
+int hrir_sparsify_device(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
+                         const double* sigma, const double* lambda, int32_t target_nnze, double threshold,
+                         int32_t k, int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out,
+                         double* err_db_out);
+int hrir_tune_sigma_device(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
+                           const double* grid, int32_t n_grid, double lambda, int32_t target_nnze,
+                           double threshold, double* sigma_out, double* sd_out);
+
 /* ------------------------------------------------------------------------
  * Render plan: the resonance filter and the sparse tap table on the device.
  * (Eq. (2) rendered as (s * f) * g; Sec. IV-F: cost proportional to the

@@ -147,6 +147,10 @@ def _load() -> ctypes.CDLL:
                                   P_i32, P_f, P_i32, P_d, P_d]),
         "hrir_tune_sigma": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_int32, c_double,
                                     P_d, P_d]),
+        "hrir_sparsify_device": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, c_int32, P_d, P_d, c_int32, c_double,
+                                         c_int32, P_i32, P_f, P_i32, P_d, P_d]),
+        "hrir_tune_sigma_device": (c_int, [P_d, c_int32, c_int32, P_d, c_int32, P_d, c_int32, c_double, c_int32,
+                                           c_double, P_d, P_d]),
         "spconv_plan_topk": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p]),
         "spconv_plan_read": (c_int, [c_void_p, c_int32, c_int32, P_i32, P_f]),
         "moving_create": (c_int, [c_void_p, c_int32, c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
@@ -177,7 +181,8 @@ EXPORTED = ("hrir_last_error", "hrir_factorize", "spconv_plan", "spconv_plan_mul
             "fftola_render", "fftola_info", "fftola_destroy", "spconv_plan_shape", "spconv_autotune",
             "spconv_plan_device", "block_streams_create", "block_streams_reset", "block_render",
             "block_streams_destroy", "stream_open", "stream_submit", "stream_end", "stream_poll", "stream_info",
-            "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma",
+            "stream_close", "stream_loadgen", "hrir_sparsify", "hrir_tune_sigma", "hrir_sparsify_device",
+            "hrir_tune_sigma_device",
             "spconv_plan_topk", "spconv_plan_read", "moving_create", "moving_render", "moving_info",
             "moving_destroy", "surrogate_select", "mlp_create", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_grads",
             "mlp_train", "mlp_destroy")
@@ -252,11 +257,12 @@ _TRANSFORMS = {"I": HRIR_D_IDENTITY, "C": HRIR_D_CONV, "W": HRIR_D_WINDOW}
 
 
 def sparsify(X, f, k: int, transform: str = "I", sigma=None, lam=None, target_nnze: int = 0,
-             threshold: float = 1e-4) -> dict:
-    """The paper's sparsifier (hrir_sparsify): per-row L1-NNLS with the
-    resonance filter f fixed, transform 'I', 'C' or 'W' (sigma per row or a
-    scalar), lam per row / scalar, or None to search lambda for target_nnze.
-    Returns p, g (k-slot tap table), nnze, lambda, err_db."""
+             threshold: float = 1e-4, device: bool = False) -> dict:
+    """The paper's sparsifier (hrir_sparsify, or hrir_sparsify_device with
+    device=True): per-row L1-NNLS with the resonance filter f fixed,
+    transform 'I', 'C' or 'W' (sigma per row or a scalar), lam per row /
+    scalar, or None to search lambda for target_nnze.  Returns p, g (k-slot
+    tap table), nnze, lambda, err_db."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     f = np.ascontiguousarray(f, dtype=np.float64)
     n, m = X.shape
@@ -267,27 +273,29 @@ def sparsify(X, f, k: int, transform: str = "I", sigma=None, lam=None, target_nn
     nnze = np.empty(n, dtype=np.int32)
     lam_out = np.empty(n)
     err = np.empty(n)
-    _check(_lib.hrir_sparsify(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _TRANSFORMS[transform],
+    fn = _lib.hrir_sparsify_device if device else _lib.hrir_sparsify
+    _check(fn(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _TRANSFORMS[transform],
                               None if sig is None else _ptr(sig, c_double), None if la is None else _ptr(la, c_double),
                               int(target_nnze), float(threshold), int(k), _ptr(p, c_int32), _ptr(g, c_float),
                               _ptr(nnze, c_int32), _ptr(lam_out, c_double), _ptr(err, c_double)))
     return {"p": p, "g": g, "nnze": nnze, "lambda": lam_out, "err_db": err}
 
 
-def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4, target_nnze: int = 0):
+def tune_sigma(X, f, grid, lam: float = 0.0, threshold: float = 1e-4, target_nnze: int = 0, device: bool = False):
     """Per-row window bandwidth from grid minimising spectral distortion
-    (hrir_tune_sigma): each bandwidth's solution at lambda = lam, or, with
-    target_nnze > 0, at the searched lambda that keeps at most target_nnze
-    entries.  Returns (sigma, sd)."""
+    (hrir_tune_sigma, or hrir_tune_sigma_device with device=True): each
+    bandwidth's solution at lambda = lam, or, with target_nnze > 0, at the
+    searched lambda that keeps at most target_nnze entries.  Returns
+    (sigma, sd)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     f = np.ascontiguousarray(f, dtype=np.float64)
     gr = np.ascontiguousarray(grid, dtype=np.float64)
     n, m = X.shape
     sig = np.empty(n)
     sd = np.empty(n)
-    _check(_lib.hrir_tune_sigma(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _ptr(gr, c_double), gr.size,
-                                float(lam), int(target_nnze), float(threshold), _ptr(sig, c_double),
-                                _ptr(sd, c_double)))
+    fn = _lib.hrir_tune_sigma_device if device else _lib.hrir_tune_sigma
+    _check(fn(_ptr(X, c_double), n, m, _ptr(f, c_double), f.size, _ptr(gr, c_double), gr.size, float(lam),
+              int(target_nnze), float(threshold), _ptr(sig, c_double), _ptr(sd, c_double)))
     return sig, sd
 
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrir.so")
 
 SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftola.hip", "block.hip", "render_moving.hip", "mlp.hip",
-           "factorize_device.hip", "autotune.cpp", "server.cpp", "loadgen.cpp", "factorize.cpp", "sparsify.cpp",
+           "factorize_device.hip", "l1_device.hip", "autotune.cpp", "server.cpp", "loadgen.cpp", "factorize.cpp", "sparsify.cpp",
            "errors.cpp"]
 
 # Per-file extra flags.  The register-window kernel dispatches taps through a
@@ -24,7 +24,9 @@ SOURCES = ["render.hip", "render_quad.hip", "render_rw.hip", "dense.hip", "fftol
 # phis copy the accumulators after every tap).
 EXTRA = {"render_rw.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"],
          # the device factorization keeps the host code's rounding: no fused multiply-adds
-         "factorize_device.hip": ["-ffp-contract=off"]}
+         "factorize_device.hip": ["-ffp-contract=off"],
+         # likewise the device L1-NNLS solves
+         "l1_device.hip": ["-ffp-contract=off"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -61,9 +61,11 @@ bool spd_solve(std::vector<double>& H, int s, double* rhs) {
         for (int q = 0; q < rr; ++q) v -= H[rr * s + q] * rhs[q];
         rhs[rr] = v / H[rr * s + rr];
     }
+    // back substitution, each row's terms from the last unknown down (the
+    // order a column-at-a-time solve on the device takes too)
     for (int rr = s - 1; rr >= 0; --rr) {
         double v = rhs[rr];
-        for (int q = rr + 1; q < s; ++q) v -= H[q * s + rr] * rhs[q];
+        for (int q = s - 1; q > rr; --q) v -= H[q * s + rr] * rhs[q];
         rhs[rr] = v / H[rr * s + rr];
     }
     return true;

@@ -30,6 +30,18 @@ double l1_weight(double lambda0, int t, int T);
 int factorize_iterate_device(const double* X, int n, int m, int lf, int iters, double lambda0, double* G,
                              double* f, double* cost);
 
+// The L1-NNLS solves of the sparsifier on the current GPU (l1_device.hip):
+// problem p minimises 1/2 g^T H_d g - (c0_p - lambda_p / 2)^T g over g >= 0
+// with H_d = H + design[p] * s * s (host f64[n_designs][s][s]) and c0_p = c0
+// + p * s (host), at lambda[p] (host, or null: the sparsifier's lambda search
+// for at most `target` entries), then discards entries <= thresh.  Outputs
+// (host): g_out f64[n_prob][s], lambda_out f64[n_prob], nnze_out i32[n_prob].
+// Same steps as the host's solve (nnls_normal, the bisection).  Status code
+// as in hrir.h; s <= 256.
+int l1_solve_device(const double* H, int n_designs, int s, const double* c0, const int* design, int n_prob,
+                    const double* lambda, int target, double thresh, double* g_out, double* lambda_out,
+                    int* nnze_out);
+
 // Lawson-Hanson active-set solution of min 1/2 y^T H y - c^T y over y >= 0,
 // H the s x s normal matrix.  Status code as in hrir.h.
 int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y);

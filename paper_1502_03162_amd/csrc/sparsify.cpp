@@ -190,6 +190,50 @@ void convolve(const double* f, int lf, const double* g, int lg, double* y) {
             for (int q = 0; q < lf; ++q) y[j + q] += f[q] * g[j];
 }
 
+// Writes row i's tap table (the k largest kept entries, ties to the lower
+// position, ascending positions, padded with (0, 0)) and its error.
+void finish_row(const double* X, int m, const double* f, int lf, int lg, int k, int64_t i, const double* g,
+                int nz, double lam, int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out,
+                double* err_db_out) {
+    std::vector<int> idx;
+    for (int j = 0; j < lg; ++j)
+        if (g[j] != 0.0) idx.push_back(j);
+    if ((int)idx.size() > k) {
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return g[a] > g[b]; });
+        idx.resize(k);
+        std::sort(idx.begin(), idx.end());
+    }
+    std::vector<double> gk(lg, 0.0);
+    for (int a = 0; a < k; ++a) {
+        const bool real = a < (int)idx.size();
+        p_out[(size_t)i * k + a] = real ? idx[a] : 0;
+        g_out[(size_t)i * k + a] = real ? (float)g[idx[a]] : 0.0f;
+        if (real) gk[idx[a]] = g[idx[a]];
+    }
+    if (nnze_out) nnze_out[i] = nz;
+    if (lambda_out) lambda_out[i] = lam;
+    if (err_db_out) {
+        const double* x = X + (size_t)i * m;
+        std::vector<double> y(m);
+        convolve(f, lf, gk.data(), lg, y.data());
+        double e = 0.0, ex = 0.0;
+        for (int t = 0; t < m; ++t) {
+            e += (x[t] - y[t]) * (x[t] - y[t]);
+            ex += x[t] * x[t];
+        }
+        err_db_out[i] = (ex > 0.0 && e > 0.0) ? 10.0 * std::log10(e / ex) : (e > 0.0 ? INFINITY : -INFINITY);
+    }
+}
+
+// Every distinct design's H, concatenated ([n_designs][lg][lg]), for the
+// device solver.
+std::vector<double> stack_h(const std::vector<Design>& designs, int lg) {
+    std::vector<double> H(designs.size() * (size_t)lg * lg);
+    for (size_t u = 0; u < designs.size(); ++u)
+        std::copy(designs[u].H.begin(), designs[u].H.end(), H.begin() + u * (size_t)lg * lg);
+    return H;
+}
+
 int check_common(const double* X, int n, int m, const double* f, int lf, const char* fn) {
     if (!X || !f) return fail(HRIR_EINVAL, "%s: null pointer", fn);
     if (n < 1 || lf < 1 || m < lf) return fail(HRIR_EINVAL, "%s: need n >= 1 and 1 <= lf <= m", fn);
@@ -206,10 +250,12 @@ int check_common(const double* X, int n, int m, const double* f, int lf, const c
 
 using hrir::fail;
 
-extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
-                             const double* sigma, const double* lambda, int32_t target_nnze, double threshold,
-                             int32_t k, int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out,
-                             double* err_db_out) {
+namespace {
+
+int sparsify_impl(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
+                  const double* sigma, const double* lambda, int32_t target_nnze, double threshold, int32_t k,
+                  int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out, double* err_db_out,
+                  bool device) {
     hrir::clear_error();
     int rc = hrir::check_common(X, n, m, f, lf, "hrir_sparsify");
     if (rc) return rc;
@@ -252,6 +298,25 @@ extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double
         hrir::build_design(designs[u], f, lf, lg, transform, keys[u]);
     });
 
+    if (device) {
+        // the solves on the GPU, everything around them on the host
+        std::vector<double> C((size_t)n * lg), G((size_t)n * lg), lam(n);
+        std::vector<int> nz(n);
+        hrir::parallel_for(n, [&](int64_t i) {
+            std::vector<double> c0;
+            hrir::design_rhs(designs[which[i]], X + (size_t)i * m, c0);
+            std::copy(c0.begin(), c0.end(), C.begin() + i * lg);
+        });
+        const std::vector<double> Hs = hrir::stack_h(designs, lg);
+        rc = hrir::l1_solve_device(Hs.data(), (int)designs.size(), lg, C.data(), which.data(), n, lambda,
+                                   target_nnze, threshold, G.data(), lam.data(), nz.data());
+        if (rc) return rc;
+        hrir::parallel_for(n, [&](int64_t i) {
+            hrir::finish_row(X, m, f, lf, lg, k, i, G.data() + i * lg, nz[i], lam[i], p_out, g_out, nnze_out,
+                             lambda_out, err_db_out);
+        });
+        return HRIR_OK;
+    }
     std::vector<int> status(n, 0);
     hrir::parallel_for(n, [&](int64_t i) {
         const hrir::Design& d = designs[which[i]];
@@ -268,44 +333,36 @@ extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double
         }
         status[i] = st;
         if (st) return;
-        // the k largest kept entries (ties to the lower position), ascending positions
-        std::vector<int> idx;
-        for (int j = 0; j < lg; ++j)
-            if (g[j] != 0.0) idx.push_back(j);
-        if ((int)idx.size() > k) {
-            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return g[a] > g[b]; });
-            idx.resize(k);
-            std::sort(idx.begin(), idx.end());
-        }
-        std::vector<double> gk(lg, 0.0);
-        for (int a = 0; a < k; ++a) {
-            const bool real = a < (int)idx.size();
-            p_out[(size_t)i * k + a] = real ? idx[a] : 0;
-            g_out[(size_t)i * k + a] = real ? (float)g[idx[a]] : 0.0f;
-            if (real) gk[idx[a]] = g[idx[a]];
-        }
-        if (nnze_out) nnze_out[i] = nz;
-        if (lambda_out) lambda_out[i] = lam;
-        if (err_db_out) {
-            const double* x = X + (size_t)i * m;
-            std::vector<double> y(m);
-            hrir::convolve(f, lf, gk.data(), lg, y.data());
-            double e = 0.0, ex = 0.0;
-            for (int t = 0; t < m; ++t) {
-                e += (x[t] - y[t]) * (x[t] - y[t]);
-                ex += x[t] * x[t];
-            }
-            err_db_out[i] = (ex > 0.0 && e > 0.0) ? 10.0 * std::log10(e / ex) : (e > 0.0 ? INFINITY : -INFINITY);
-        }
+        hrir::finish_row(X, m, f, lf, lg, k, i, g.data(), nz, lam, p_out, g_out, nnze_out, lambda_out, err_db_out);
     });
     for (int i = 0; i < n; ++i)
         if (status[i]) return fail(status[i], "hrir_sparsify: NNLS failed on row %d", i);
     return HRIR_OK;
 }
 
-extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
-                               const double* grid, int32_t n_grid, double lambda, int32_t target_nnze,
-                               double threshold, double* sigma_out, double* sd_out) {
+}  // namespace
+
+extern "C" int hrir_sparsify(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, int32_t transform,
+                             const double* sigma, const double* lambda, int32_t target_nnze, double threshold,
+                             int32_t k, int32_t* p_out, float* g_out, int32_t* nnze_out, double* lambda_out,
+                             double* err_db_out) {
+    return sparsify_impl(X, n, m, f, lf, transform, sigma, lambda, target_nnze, threshold, k, p_out, g_out, nnze_out,
+                         lambda_out, err_db_out, false);
+}
+
+extern "C" int hrir_sparsify_device(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
+                                    int32_t transform, const double* sigma, const double* lambda,
+                                    int32_t target_nnze, double threshold, int32_t k, int32_t* p_out, float* g_out,
+                                    int32_t* nnze_out, double* lambda_out, double* err_db_out) {
+    return sparsify_impl(X, n, m, f, lf, transform, sigma, lambda, target_nnze, threshold, k, p_out, g_out, nnze_out,
+                         lambda_out, err_db_out, true);
+}
+
+namespace {
+
+int tune_sigma_impl(const double* X, int32_t n, int32_t m, const double* f, int32_t lf, const double* grid,
+                    int32_t n_grid, double lambda, int32_t target_nnze, double threshold, double* sigma_out,
+                    double* sd_out, bool device) {
     hrir::clear_error();
     int rc = hrir::check_common(X, n, m, f, lf, "hrir_tune_sigma");
     if (rc) return rc;
@@ -321,24 +378,52 @@ extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const doub
         hrir::build_design(designs[u], f, lf, lg, HRIR_D_WINDOW, grid[u]);
     });
     const hrir::Dft dft(m);
+    // the solution of row i at grid entry u: on the device all n * n_grid
+    // problems at once (problem i * n_grid + u), else per row on the host
+    std::vector<double> G;
+    if (device) {
+        const int64_t np = (int64_t)n * n_grid;
+        if (np > INT32_MAX / 2) return fail(HRIR_EINVAL, "hrir_tune_sigma: too many problems");
+        std::vector<double> C((size_t)np * lg), lam(np, lambda), lam_out(np);
+        std::vector<int> which(np), nz(np);
+        hrir::parallel_for(n, [&](int64_t i) {
+            std::vector<double> c0;
+            for (int u = 0; u < n_grid; ++u) {
+                hrir::design_rhs(designs[u], X + (size_t)i * m, c0);
+                std::copy(c0.begin(), c0.end(), C.begin() + (i * n_grid + u) * lg);
+                which[i * n_grid + u] = u;
+            }
+        });
+        G.resize((size_t)np * lg);
+        const std::vector<double> Hs = hrir::stack_h(designs, lg);
+        rc = hrir::l1_solve_device(Hs.data(), n_grid, lg, C.data(), which.data(), (int)np,
+                                   target_nnze > 0 ? nullptr : lam.data(), target_nnze, threshold, G.data(),
+                                   lam_out.data(), nz.data());
+        if (rc) return rc;
+    }
     std::vector<int> status(n, 0);
     hrir::parallel_for(n, [&](int64_t i) {
         const double* x = X + (size_t)i * m;
-        std::vector<double> c0, c, g(lg), y(m), mx(m), my(m);
+        std::vector<double> c0, c, gh(lg), y(m), mx(m), my(m);
         dft.floored_magnitude(x, mx.data());
         double best = INFINITY, best_s = grid[0];
         for (int u = 0; u < n_grid; ++u) {
-            hrir::design_rhs(designs[u], x, c0);
-            int nz = 0;
-            double lam = lambda;
-            const int st = target_nnze > 0
-                               ? hrir::search_lambda(designs[u], c0, target_nnze, threshold, g.data(), &lam, &nz)
-                               : hrir::solve_one(designs[u], c0, lambda, threshold, c, g.data(), &nz);
-            if (st) {
-                status[i] = st;
-                return;
+            const double* g = gh.data();
+            if (device) {
+                g = G.data() + (i * n_grid + u) * lg;
+            } else {
+                hrir::design_rhs(designs[u], x, c0);
+                int nz = 0;
+                double lam = lambda;
+                const int st = target_nnze > 0
+                                   ? hrir::search_lambda(designs[u], c0, target_nnze, threshold, gh.data(), &lam, &nz)
+                                   : hrir::solve_one(designs[u], c0, lambda, threshold, c, gh.data(), &nz);
+                if (st) {
+                    status[i] = st;
+                    return;
+                }
             }
-            hrir::convolve(f, lf, g.data(), lg, y.data());
+            hrir::convolve(f, lf, g, lg, y.data());
             dft.floored_magnitude(y.data(), my.data());
             const double sd = hrir::spectral_distortion(mx.data(), my.data(), m);
             if (sd < best) {
@@ -352,6 +437,20 @@ extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const doub
     for (int i = 0; i < n; ++i)
         if (status[i]) return fail(status[i], "hrir_tune_sigma: NNLS failed on row %d", i);
     return HRIR_OK;
+}
+
+}  // namespace
+
+extern "C" int hrir_tune_sigma(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
+                               const double* grid, int32_t n_grid, double lambda, int32_t target_nnze,
+                               double threshold, double* sigma_out, double* sd_out) {
+    return tune_sigma_impl(X, n, m, f, lf, grid, n_grid, lambda, target_nnze, threshold, sigma_out, sd_out, false);
+}
+
+extern "C" int hrir_tune_sigma_device(const double* X, int32_t n, int32_t m, const double* f, int32_t lf,
+                                      const double* grid, int32_t n_grid, double lambda, int32_t target_nnze,
+                                      double threshold, double* sigma_out, double* sd_out) {
+    return tune_sigma_impl(X, n, m, f, lf, grid, n_grid, lambda, target_nnze, threshold, sigma_out, sd_out, true);
 }
 
 // Fallback rule of the surrogate: directions are compared by the angle between
