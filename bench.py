@@ -461,20 +461,19 @@ def bench_quality(H, hs, fac, lf, lg, k, fact_iters, paper_iters):
 
 def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
     """Direction-conditioned surrogate: an MLP (sin az, cos az, sin el, cos el)
-    -> 4 x 256 -> 2 x 200 dense reflection taps, trained on the dense
-    factorization G of 1,000 of the 1,250 directions; the 250 held out are
-    judged against their own factorization (top-16 of the prediction against
-    the factorization's 16-tap filter).  Then 128 moving sources of 262,144
+    -> 4 x 256 -> 2 x 200 dense reflection taps, trained on 1,000 of the 1,250
+    directions, once with the squared error on the dense factorization G and
+    once with the HRIR reconstruction error ||f * y - h||^2 of its dense
+    output; the 250 held out are judged against their own factorization
+    (top-16 of the prediction against the factorization's 16-tap filter) and
+    against their true HRIR, beside the measured references (nearest measured
+    direction, best grid neighbour).  Then 128 moving sources of 262,144
     samples whose direction changes every 512 samples (64-sample crossfade):
     every segment's direction goes through the network on the GPU, top-16
     into plan rows, and the fallback rule (nearest held-out direction worse
     than -30 dB -> nearest measured filter) picks predicted or measured rows."""
     import synth
     D = hs.az.size
-    G = fac["G"]
-    T = np.zeros((D, 400), np.float32)
-    T[:, :lg] = G[0::2]
-    T[:, 200:200 + lg] = G[1::2]
 
     def feats(az, el):
         return np.stack([np.sin(az), np.cos(az), np.sin(el), np.cos(el)], axis=-1).astype(np.float32)
@@ -485,53 +484,141 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
     sizes = [4, 256, 256, 256, 256, 400]
     n_src, N, seg, fade = 128, 262144, 512, 64
     n_seg = N // seg
-    net = H.Mlp(sizes, max_batch=n_src * n_seg)
-    net.set_params(synth.mlp_params(5, sizes))
-    x_tr = torch.from_numpy(X[tr]).to(dev)
-    t_tr = torch.from_numpy(T[tr]).to(dev)
-    t0 = time.perf_counter()
-    losses = []
-    for chunk in range(args.surrogate_steps // 1000):
-        losses.append(net.train(x_tr, t_tr, 1000, 1e-3))
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    log(f"surrogate: {args.surrogate_steps} Adam steps in {train_s:.2f} s, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
-
-    # held-out quality: top-16 of the prediction vs the factorization's filter
+    f64 = fac["f"]
     K = fac["p"].shape[1]
     n_meas = 2 * D
-    y_va = torch.empty((va.size, 400), device=dev)
-    net.forward(torch.from_numpy(X[va]).to(dev), y_va)
-    plan_v = H.Plan(r, np.concatenate([fac["p"], np.zeros((2 * va.size, K), np.int32)]),
-                    np.concatenate([fac["g"], np.zeros((2 * va.size, K), np.float32)]), lg)
-    H.plan_topk(plan_v, n_meas, y_va.view(2 * va.size, 200), lg)
-    pp, gg = H.plan_read(plan_v, n_meas, 2 * va.size)
-    plan_v.close()
-    f64 = fac["f"]
+    x_tr = torch.from_numpy(X[tr]).to(dev)
+
+    # Reconstruction-loss training: with T = T(f) (200 x 169) and the
+    # Cholesky factor L of T^T T, ||T y - h||^2 = ||L^T y - L^-1 T^T h||^2 +
+    # const, so training the network on the outputs y' = y L (row form) with
+    # MSE against t' = (L^-1 T^T h)^T minimises the HRIR reconstruction error
+    # of its dense output; afterwards the output layer is mapped back once,
+    # W = W' L^-1, b = b' L^-1, so the network predicts y itself.
+    m = lf + lg - 1
+    Tf = np.zeros((m, lg))
+    for j in range(lg):
+        Tf[j:j + lf, j] = f64
+    Lc = np.linalg.cholesky(Tf.T @ Tf)
+    Linv = np.linalg.inv(Lc)
+    Tr = np.zeros((D, 400), np.float32)
+    for e in range(2):
+        Tr[:, 200 * e:200 * e + lg] = np.linalg.solve(Lc, Tf.T @ hs.h[e::2].T).T
+
+    def train(targets, label):
+        net = H.Mlp(sizes, max_batch=n_src * n_seg)
+        net.set_params(synth.mlp_params(5, sizes))
+        t_tr = torch.from_numpy(targets[tr]).to(dev)
+        t0 = time.perf_counter()
+        losses = [net.train(x_tr, t_tr, 1000, 1e-3) for _ in range(args.surrogate_steps // 1000)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"surrogate ({label}): {args.surrogate_steps} Adam steps in {dt:.2f} s, loss {losses[0]:.3g} -> "
+            f"{losses[-1]:.3g}")
+        return net, losses, dt
 
     def dense(p, g):
         out = np.zeros(lg)
         np.add.at(out, p, g.astype(np.float64))
         return out
 
-    e_fact = np.zeros((va.size, 2))
-    e_nn = np.zeros((va.size, 2))
+    def edb(a, ref):
+        return 10 * np.log10(np.sum((a - ref) ** 2) / np.sum(ref ** 2))
 
     def unit(a, e):
         return np.stack([np.sin(a), np.cos(a) * np.cos(e), np.cos(a) * np.sin(e)], axis=-1)
 
+    # measured references for each held-out filter: the factorization's own
+    # 16 taps, the nearest measured (training) direction, and the best of the
+    # training directions next to it on the grid (an upper bound for any rule
+    # that copies a measured filter)
+    ua, ue = np.unique(hs.az), np.unique(hs.el)
+    ia, ie = np.searchsorted(ua, hs.az), np.searchsorted(ue, hs.el)
+    cell = {(int(a), int(b)): d for d, (a, b) in enumerate(zip(ia, ie))}
+    in_tr = np.zeros(D, bool)
+    in_tr[tr] = True
     Ut = unit(hs.az[tr], hs.el[tr])
+    rec = lambda d, e: np.convolve(f64, dense(fac["p"][2 * d + e], fac["g"][2 * d + e]))
+    near = np.array([tr[int(np.argmax(Ut @ unit(hs.az[v], hs.el[v])))] for v in va])
+    ref = {k: np.zeros((va.size, 2)) for k in ("fact_vs_true", "nearest_vs_fact", "nearest_vs_true",
+                                               "best_neighbour_vs_true")}
+    same_support = np.zeros((va.size, 2), bool)
     for i, v in enumerate(va):
-        m = tr[int(np.argmax(Ut @ unit(hs.az[v], hs.el[v])))]
+        nb = [cell[(int(ia[v]) + da, int(ie[v]) + de)] for da in (-1, 0, 1) for de in (-1, 0, 1)
+              if (da or de) and (int(ia[v]) + da, int(ie[v]) + de) in cell]
+        nb = [d for d in nb if in_tr[d]]
         for e in range(2):
-            ref = np.convolve(f64, dense(fac["p"][2 * v + e], fac["g"][2 * v + e]))
-            pred = np.convolve(f64, dense(pp[2 * i + e], gg[2 * i + e]))
-            near = np.convolve(f64, dense(fac["p"][2 * m + e], fac["g"][2 * m + e]))
-            e_fact[i, e] = 10 * np.log10(np.sum((pred - ref) ** 2) / np.sum(ref ** 2))
-            e_nn[i, e] = 10 * np.log10(np.sum((near - ref) ** 2) / np.sum(ref ** 2))
+            h = hs.h[2 * v + e]
+            own = rec(v, e)
+            ref["fact_vs_true"][i, e] = edb(own, h)
+            ref["nearest_vs_fact"][i, e] = edb(rec(near[i], e), own)
+            ref["nearest_vs_true"][i, e] = edb(rec(near[i], e), h)
+            ref["best_neighbour_vs_true"][i, e] = min((edb(rec(d, e), h) for d in nb), default=np.inf)
+            same_support[i, e] = any(np.array_equal(np.sort(fac["p"][2 * d + e]), np.sort(fac["p"][2 * v + e]))
+                                     for d in nb)
+
+    def judge(net):
+        """Top-16 of the network's prediction for every held-out direction (on
+        the device, into plan rows) against the factorization and the true HRIR."""
+        y_va = torch.empty((va.size, 400), device=dev)
+        net.forward(torch.from_numpy(X[va]).to(dev), y_va)
+        plan_v = H.Plan(r, np.concatenate([fac["p"], np.zeros((2 * va.size, K), np.int32)]),
+                        np.concatenate([fac["g"], np.zeros((2 * va.size, K), np.float32)]), lg)
+        H.plan_topk(plan_v, n_meas, y_va.view(2 * va.size, 200), lg)
+        pp, gg = H.plan_read(plan_v, n_meas, 2 * va.size)
+        plan_v.close()
+        e_fact, e_true = np.zeros((va.size, 2)), np.zeros((va.size, 2))
+        for i, v in enumerate(va):
+            for e in range(2):
+                pred = np.convolve(f64, dense(pp[2 * i + e], gg[2 * i + e]))
+                e_fact[i, e] = edb(pred, rec(v, e))
+                e_true[i, e] = edb(pred, hs.h[2 * v + e])
+        return e_fact, e_true
+
+    def stats(x):
+        return {"median": float(np.median(x)), "mean": float(np.mean(x)), "worst": float(np.max(x)),
+                "frac_below_-30": float(np.mean(x < -30))}
+
+    Tg = np.zeros((D, 400), np.float32)
+    Tg[:, :lg] = fac["G"][0::2]
+    Tg[:, 200:200 + lg] = fac["G"][1::2]
+    variants, nets = {}, {}
+    for label, targets in (("mse_on_G", Tg), ("hrir_reconstruction", Tr)):
+        net, losses, dt = train(targets, label)
+        if label == "hrir_reconstruction":
+            params = net.get_params()
+            W, b = params[-1]
+            W, b = W.astype(np.float64), b.astype(np.float64)
+            for e in range(2):
+                cols = slice(200 * e, 200 * e + lg)
+                W[:, cols] = W[:, cols] @ Linv
+                b[cols] = b[cols] @ Linv
+            params[-1] = (W, b)
+            net.set_params(params)
+        e_fact, e_true = judge(net)
+        variants[label] = {"train_s": dt, "loss_first": losses[0], "loss_last": losses[-1],
+                           "heldout_E_dB_vs_factorization": stats(e_fact), "heldout_E_dB_vs_true_hrir": stats(e_true),
+                           "_e_fact": e_fact}
+        nets[label] = net
+        log(f"surrogate ({label}) held-out E_dB median vs factorization {np.median(e_fact):.2f}, vs true HRIR "
+            f"{np.median(e_true):.2f}; below -30 dB: {100 * np.mean(e_fact < -30):.1f} %")
+    log(f"held-out references vs true HRIR (median): factorization's own 16 taps "
+        f"{np.median(ref['fact_vs_true']):.2f}, nearest measured {np.median(ref['nearest_vs_true']):.2f}, "
+        f"best grid neighbour {np.median(ref['best_neighbour_vs_true']):.2f} (below -30 dB: "
+        f"{100 * np.mean(ref['best_neighbour_vs_true'] < -30):.1f} %); a neighbour with the same support: "
+        f"{100 * np.mean(same_support):.1f} %")
+    # serve with the variant closer to the factorization at the held-out directions
+    use = min(variants, key=lambda k: np.median(variants[k]["_e_fact"]))
+    net = nets.pop(use)
+    for other in nets.values():
+        other.close()
+    e_fact = variants[use]["_e_fact"]
+    for v in variants.values():
+        v.pop("_e_fact")
     val_err = e_fact.max(axis=1)
-    log(f"surrogate held-out E_dB vs factorization: median {np.median(e_fact):.2f}, "
-        f"nearest measured filter {np.median(e_nn):.2f}")
+    train_s = variants[use]["train_s"]
+    losses = [variants[use]["loss_first"], variants[use]["loss_last"]]
+    e_nn = ref["nearest_vs_fact"]
 
     # moving sources: smooth trajectories through the measured range
     rng = np.random.default_rng(77)
@@ -576,11 +663,11 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
                        "trained on 1,000 of 1,250 directions, 250 held out; 128 moving sources x 262,144 samples, "
                        "direction every 512 samples, 64-sample crossfade, K = 16",
            "params": net.n_params, "train_steps": args.surrogate_steps, "train_s": train_s,
-           "loss_first": losses[0], "loss_last": losses[-1],
-           "heldout_E_dB_vs_factorization": {"median": float(np.median(e_fact)), "mean": float(np.mean(e_fact)),
-                                             "worst": float(np.max(e_fact)),
-                                             "frac_below_-30": float(np.mean(e_fact < -30))},
+           "loss_first": losses[0], "loss_last": losses[-1], "served_variant": use, "variants": variants,
+           "heldout_E_dB_vs_factorization": stats(e_fact),
            "nearest_measured_E_dB": {"median": float(np.median(e_nn)), "mean": float(np.mean(e_nn))},
+           "heldout_references_vs_true_hrir": {k: stats(v) for k, v in ref.items() if k.endswith("true")},
+           "heldout_with_a_neighbour_of_the_same_support": float(np.mean(same_support)),
            "fallback_fraction": float(np.mean(choice >= 0)),
            "inference": {"queries": nq, "ms": inf_ms, "queries_per_s": nq / (inf_ms * 1e-3)},
            "moving_render": {"ms_per_step": mms, "output_samples_per_s": n_out / (mms * 1e-3),
