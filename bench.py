@@ -45,16 +45,20 @@ def log(msg):
     note(msg)
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources of the default render kernel (a counter summary
-    taken on other sources is not reported)."""
+QUAD_SOURCES = ("render.hip", "render_quad.hip", "render_quad.h", "render_common.h")
+MOVING_SOURCES = ("render_moving.hip", "render_quad.h", "render_common.h")
+
+
+def kernel_source_hash(files=QUAD_SOURCES) -> str:
+    """Hash of a render kernel's sources (a counter summary taken on other
+    sources is not reported)."""
     h = hashlib.sha256()
-    for fn in ("render.hip", "render_quad.hip", "render_quad.h", "render_common.h"):
+    for fn in files:
         h.update(open(os.path.join(ROOT, "paper_1502_03162_amd", "csrc", fn), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str):
+def measured_traffic(name: str, files=QUAD_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source (else None)."""
     fn = os.path.join(ROOT, "profiles", "traffic.json")
@@ -64,7 +68,7 @@ def measured_traffic(name: str):
         d = json.load(open(fn)).get(name)
     except (OSError, ValueError):
         return None
-    if not d or d.get("source_hash") != kernel_source_hash():
+    if not d or d.get("source_hash") != kernel_source_hash(files):
         return None
     return d.get("bytes_per_launch")
 
@@ -188,7 +192,8 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
     return {"workload": "512 pink sources, lengths log-uniform in [4096, 1048576], 1..8 directions x 2 ears, K=16, "
                         "one persistent launch replayed from a HIP graph",
             "output_samples": n_out, "rows": len(jobs), "ms_per_step": ms, "value": n_out / (ms * 1e-3),
-            "unit": "output samples/s", "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
+            "unit": "output samples/s", "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "algorithmic_bytes": alg,
+            "traffic": measured_traffic("render_uneven"),
             "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile": best["tile"], "group": best["group"],
             "threads_per_workgroup": 256 if best["flags"] & H.SPCONV_WG256 else 512,
             "persistent_grid": info["grid"], "tiles": info["tiles"], "autotune_s": tune_s,
@@ -671,7 +676,9 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
            "fallback_fraction": float(np.mean(choice >= 0)),
            "inference": {"queries": nq, "ms": inf_ms, "queries_per_s": nq / (inf_ms * 1e-3)},
            "moving_render": {"ms_per_step": mms, "output_samples_per_s": n_out / (mms * 1e-3),
-                             "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "kernel": "k_render_moving<32,16,2>",
+                             "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "algorithmic_bytes": alg,
+                             "traffic_tile_2560": measured_traffic("render_moving", MOVING_SOURCES),
+                             "kernel": "k_render_moving<32,16,2>",
                              "tile": best_tile, "ms_by_tile": {str(k): v for k, v in by_tile.items()}}}
     log(f"surrogate inference: {nq} directions in {inf_ms:.3f} ms; fallback {100 * np.mean(choice >= 0):.1f} %; "
         f"moving render {mms:.3f} ms, {n_out / (mms * 1e-3):.3g} samples/s")
