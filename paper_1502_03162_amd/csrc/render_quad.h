@@ -20,6 +20,7 @@ static_assert(kQChunk == 1024, "quad chunk");
 static_assert(kQPass * kQThreads * kZpt >= kQuadTileMax + 2048 + 3, "FIR passes cover the largest tile");
 constexpr int kQSmallCover = kQPass * 256 * kZpt;   // z values the FIR of a 256-thread workgroup covers
 static_assert(kZpt == 8, "the copy stores rotate 8 values per lane by lane / 8");
+typedef float f8v __attribute__((ext_vector_type(8)));
 
 // Floats per shifted copy: holds m < TB + H (+ padding so that the copies
 // start on different banks).
@@ -109,24 +110,28 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
             // same element a, 8 lanes would share each bank.  Store k writes
             // element (k + lane / 8) mod 8 instead, which puts the 64 lanes
             // on 64 different banks; the lane's values are rotated by
-            // lane / 8 to match (a three-stage barrel shift).
+            // lane / 8 to match: a vector of 8 rotated by 1, 2 and 4 under
+            // the bits of g, 8 selects per stage on one condition.  (On an
+            // array indexed inside a loop the compiler merges the stages into
+            // an 8-way select per value, about five times the instructions.)
             const int g = (tid >> 3) & 7;
-            float zr[kZpt];
+            f8v zr = {zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3], zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]};
+            if (g & 1) zr = __builtin_shufflevector(zr, zr, 1, 2, 3, 4, 5, 6, 7, 0);
+            if (g & 2) zr = __builtin_shufflevector(zr, zr, 2, 3, 4, 5, 6, 7, 0, 1);
+            if (g & 4) zr = __builtin_shufflevector(zr, zr, 4, 5, 6, 7, 0, 1, 2, 3);
+            // zr[k] = zz[ps][(k + g) mod 8], stored at element (k + g) mod 8.
+            // The element offsets pass through an empty asm (no instruction):
+            // seen through, they let the compiler turn the rotated stores back
+            // into fixed-offset stores of values picked by 8-way selects.
+            int ok[kZpt];
 #pragma unroll
-            for (int a = 0; a < kZpt; ++a) zr[a] = zz[ps][a];
-#pragma unroll
-            for (int b = 1; b < kZpt; b <<= 1) {
-                float t[kZpt];
-#pragma unroll
-                for (int k = 0; k < kZpt; ++k) t[k] = (g & b) ? zr[(k + b) & (kZpt - 1)] : zr[k];
-#pragma unroll
-                for (int k = 0; k < kZpt; ++k) zr[k] = t[k];
-            }
-            // zr[k] = zz[ps][(k + g) mod 8]
+            for (int k = 0; k < kZpt; ++k) ok[k] = (k + g) & (kZpt - 1);
+            asm volatile("" : "+v"(ok[0]), "+v"(ok[1]), "+v"(ok[2]), "+v"(ok[3]), "+v"(ok[4]), "+v"(ok[5]),
+                              "+v"(ok[6]), "+v"(ok[7]));
 #pragma unroll
             for (int c = 1; c < 4; ++c)
 #pragma unroll
-                for (int k = 0; k < kZpt; ++k) zc[c * CS + u0 + ((k + g) & (kZpt - 1)) - c] = zr[k];
+                for (int k = 0; k < kZpt; ++k) zc[c * CS + u0 + ok[k] - c] = zr[k];
         } else if (u0 < nz8) {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
