@@ -436,7 +436,10 @@ void block_streams_destroy(hrir_streams* streams);
  * stream_open    max_streams stream slots (1..2^20) with zeroed histories;
  *                hbm_budget bounds the device bytes of histories plus the
  *                generation ring (EINVAL if it cannot hold two generations
- *                of one maximal block).  flags: STREAM_DIRECT_LAUNCH sizes
+ *                of one maximal block); 0 sizes it as a quarter of the
+ *                device memory free at the call (hipMemGetInfo), and
+ *                ENOMEM if what the budget places on the device exceeds
+ *                the free memory.  flags: STREAM_DIRECT_LAUNCH sizes
  *                each launch to its batch (one workgroup per block) instead
  *                of replaying a HIP graph of a persistent launch;
  *                STREAM_ZERO_COPY keeps the generation ring (job tables,

@@ -617,7 +617,7 @@ class Server:
     with out a float32 array [2, n] (left, right) copied out of the server's
     buffer."""
 
-    def __init__(self, plan: Plan, max_streams: int, hbm_budget: int = 256 << 20, flags: int = 0):
+    def __init__(self, plan: Plan, max_streams: int, hbm_budget: int = 0, flags: int = 0):
         self.plan = plan
         self.max_streams = max_streams
         self.tail = plan.lf + plan.lg - 2

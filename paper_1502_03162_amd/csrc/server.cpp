@@ -442,9 +442,17 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
         return fail(HRIR_EINVAL, "stream_open: max_streams=%d outside [1, 2^20]", max_streams);
     if (flags & ~(STREAM_DIRECT_LAUNCH | STREAM_ZERO_COPY))
         return fail(HRIR_EINVAL, "stream_open: unknown flags 0x%x", flags);
+    if (hbm_budget < 0) return fail(HRIR_EINVAL, "stream_open: hbm_budget %lld < 0", (long long)hbm_budget);
     int32_t shp[3];
     int rc = spconv_plan_shape(plan, shp);
     if (rc) return rc;
+    // device memory free before anything of this server is allocated: the
+    // default budget is a quarter of it, and what the sizing below places on
+    // the device must fit in it
+    size_t dev_free = 0, dev_total = 0;
+    const hipError_t me = hipMemGetInfo(&dev_free, &dev_total);
+    if (me != hipSuccess) return fail(HRIR_EDEVICE, "stream_open: %s", hipGetErrorString(me));
+    if (hbm_budget == 0) hbm_budget = (int64_t)(dev_free / 4);
     const int lf = shp[0], lg = shp[2];
     const int tail = lf + lg - 2;
     const int64_t min_cap = std::max(kBlockMax, tail);
@@ -476,6 +484,14 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
         free_server(s);
         return fail(HRIR_EINVAL, "stream_open: hbm_budget %lld too small; at least %lld bytes are needed",
                     (long long)hbm_budget, (long long)(hist_bytes + 2 * per_gen(min_cap)));
+    }
+    // the histories are already allocated; the ring goes to the device
+    // unless it lives in pinned host memory
+    const int64_t dev_bytes = hist_bytes + ((flags & STREAM_ZERO_COPY) ? 0 : n_gens * per_gen(cap));
+    if (dev_bytes > (int64_t)dev_free) {
+        free_server(s);
+        return fail(HRIR_ENOMEM, "stream_open: the server needs %lld bytes of device memory, %lld are free",
+                    (long long)dev_bytes, (long long)dev_free);
     }
 
     s->flags = flags;

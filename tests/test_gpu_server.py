@@ -329,4 +329,30 @@ def test_argument_errors(dev):
         h.Server(plan, max_streams=0)
     with pytest.raises(h.HrirError):
         h.Server(plan, max_streams=4, flags=8)
+    with pytest.raises(h.HrirError) as ei:
+        h.Server(plan, max_streams=4, hbm_budget=-1)
+    assert ei.value.code == h.HRIR_EINVAL
+    srv = h.Server(plan, max_streams=4, hbm_budget=1 << 50)   # a bound, not an allocation
+    srv.close()
+    plan.close()
+
+
+def test_default_budget_from_free_memory(dev):
+    """hbm_budget = 0 (the binding's default) sizes the ring from the free
+    device memory: a full ring of generations, and blocks render as with an
+    explicit budget."""
+    h = H()
+    r, p, g = _taps(16, 32, 169, 16, 4)
+    plan = h.Plan(r, p, g, 169)
+    outs = []
+    for budget in (0, 1 << 30):
+        srv = h.Server(plan, max_streams=8, hbm_budget=budget)
+        assert srv.info()["generations"] >= 2
+        assert srv.submit(3, synth.white(5, 1000), 0, 1)
+        got = []
+        while not got:
+            got = srv.poll(timeout_us=-1)
+        outs.append(got[0][2])
+        srv.close()
+    assert np.array_equal(outs[0], outs[1])
     plan.close()
