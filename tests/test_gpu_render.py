@@ -7,6 +7,7 @@ every output is summed in one fixed order."""
 import numpy as np
 import pytest
 
+import fp32bound
 import oracle
 import synth
 
@@ -93,9 +94,17 @@ def test_ragged_lengths_and_shapes(dev, lf, lg, k, kernel):
     lens = [1, 2, 31, 199, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 10000]
     srcs = [synth.white(100 + i, n) for i, n in enumerate(lens)]
     jobs = [(i, (i + j) % F) for i in range(len(lens)) for j in range(2)]
-    if kernel == "regwin" and lg > 169:
-        pytest.skip("the register-window kernel serves lg <= 169")
     plan = h.Plan(r, p, g, lg)
+    if kernel == "regwin" and lg > 169:
+        # the register-window kernel serves lg <= 169: it refuses longer
+        # filters before any device work (the default kernel renders them)
+        lens = np.array([len(x) for x in srcs], dtype=np.int64)
+        off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+        with pytest.raises(h.HrirError) as e:
+            h.Batch(plan, off, lens, [(0, 0, 0)], flags=h.SPCONV_REGWIN)
+        assert e.value.code == h.HRIR_EINVAL and "lg <=" in str(e.value)
+        plan.close()
+        return
     flags = {"quad": 0, "quad256": h.SPCONV_WG256, "lds_gather": h.SPCONV_LDS_GATHER,
              "regwin": h.SPCONV_REGWIN}[kernel]
     # 256-thread workgroups cover tile + lg + 2 <= 4096 z values: at lg = 2048
@@ -278,8 +287,13 @@ def test_full_size_throughput_config_sampled(dev):
         s, f = jobs[j]
         t = np.unique(np.concatenate([[0, 1, 168, 199, L - 200, L - 1], rng.integers(0, L, 40)]))
         idx = torch.from_numpy(out_off[j] + t).to(dev)
-        got.append(out[idx].cpu().numpy())
-        ref.append(oracle.sparse_render_points(r, srcs[s], fac["p"][f], fac["g"][f].astype(np.float64), t))
+        gj = out[idx].cpu().numpy()
+        pf, gf = fac["p"][f], fac["g"][f].astype(np.float64)
+        rj = oracle.sparse_render_points(r, srcs[s], pf, gf, t)
+        # every sample within the FP32 bound of its own fma chains
+        assert np.all(np.abs(gj - rj) <= fp32bound.render_bound(r, srcs[s], pf, gf, t, 16)), (j, s, f)
+        got.append(gj)
+        ref.append(rj)
     got, ref = np.concatenate(got), np.concatenate(ref)
     e = oracle.rel_l2(got, ref)
     print(f"full-size sampled rel L2 {e:.3e} over {got.size} samples", flush=True)

@@ -8,6 +8,7 @@ import os
 import numpy as np
 import pytest
 
+import fp32bound
 import oracle
 import synth
 
@@ -96,8 +97,12 @@ def test_full_size_uneven_config_sampled(dev):
         s, f = jobs[j]
         L = plan.out_len(lens[s])
         t = np.unique(np.concatenate([[0, 1, L - 1], rng.integers(0, L, 45)]))
-        got.append(out[torch.from_numpy(out_off[j] + t).to(dev)].cpu().numpy())
-        ref.append(oracle.sparse_render_points(r, srcs[s], p[f], g[f].astype(np.float64), t))
+        gj = out[torch.from_numpy(out_off[j] + t).to(dev)].cpu().numpy()
+        rj = oracle.sparse_render_points(r, srcs[s], p[f], g[f].astype(np.float64), t)
+        # every sample within the FP32 bound of its own fma chains
+        assert np.all(np.abs(gj - rj) <= fp32bound.render_bound(r, srcs[s], p[f], g[f], t, K)), (j, s, f)
+        got.append(gj)
+        ref.append(rj)
     got, ref = np.concatenate(got), np.concatenate(ref)
     assert np.all(np.isfinite(got))
     assert oracle.rel_l2(got, ref) <= TOL

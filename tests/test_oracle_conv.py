@@ -182,3 +182,42 @@ def test_block_render_concatenation_equals_one_shot(seed):
     ref = oracle.sparse_render(r, s, p, g, lg)
     assert out.size == ref.size
     assert rel(out, ref) < 1e-13
+
+
+def _fma32_chain(terms_a, terms_b):
+    """FP32 fma chain over axis 0: acc = fl32(a_i b_i + acc), the product of
+    two FP32 values exact in FP64, one rounding per step as an fma."""
+    acc = np.zeros(terms_a.shape[1:], dtype=np.float32)
+    for a, b in zip(terms_a, terms_b):
+        acc = (a.astype(np.float64) * b.astype(np.float64) + acc.astype(np.float64)).astype(np.float32)
+    return acc
+
+
+def test_fp32_render_bound_holds_and_is_tight():
+    """The per-sample bound the GPU parity tests use (tests/fp32bound.py):
+    an FP32 emulation of the render's two fma chains (z over the lf
+    resonance taps, then the K kept taps on the rounded z) stays inside it
+    at every sample, and the worst sample comes within a factor of 200 of
+    it (2.8 % of the bound here; rounding errors add up like a random walk,
+    the bound like a straight line), so the bound is not vacuous."""
+    import fp32bound
+    rng = np.random.default_rng(5)
+    lf, lg, k = 32, 169, 16
+    r = rng.standard_normal(lf).astype(np.float32)
+    s = (rng.standard_normal(6000) * 0.3).astype(np.float32)
+    p = np.sort(rng.choice(lg, k, replace=False)).astype(np.int32)
+    g = rng.uniform(0, 1, k).astype(np.float32)
+    t = np.arange(0, s.size + lf + lg - 2, 7)
+    # z32[u] for every u the taps reach: chain over n of r[n] s[u - n]
+    umax = t.max()
+    u = np.arange(umax + 1)
+    sa = np.stack([np.where((u - n >= 0) & (u - n < s.size), s[np.clip(u - n, 0, s.size - 1)], 0).astype(np.float32)
+                   for n in range(lf)])
+    z32 = _fma32_chain(np.repeat(r[:, None], u.size, axis=1), sa)
+    zt = np.stack([np.where(t - pk >= 0, z32[np.clip(t - pk, 0, umax)], 0).astype(np.float32) for pk in p])
+    y32 = _fma32_chain(np.repeat(g[:, None], t.size, axis=1), zt)
+    y = oracle.sparse_render_points(r, s, p, g.astype(np.float64), t)
+    err = np.abs(y32.astype(np.float64) - y)
+    bound = fp32bound.render_bound(r, s, p, g, t, k)
+    assert np.all(err <= bound)
+    assert np.max(err / np.maximum(bound, 1e-300)) > 0.005
