@@ -277,9 +277,10 @@ def bench_serving(H, fac, r, lg, args):
     sig = synth.pink(4343, 1 << 20)
     rt_hz = n_streams * 48000 / 544.0            # mean block length (64 + 1024) / 2
     srv = H.Server(plan, n_streams, hbm_budget=1 << 30)
-    # four submitting threads over disjoint stream ranges: one thread cannot
-    # keep a Poisson schedule near the loop's saturation rate
-    gen = dict(n_streams=n_streams, block_min=64, block_max=1024, n_filters=2 * 1250, submit_threads=4)
+    # several submitting threads over disjoint stream ranges: one thread
+    # cannot keep a Poisson schedule near the loop's saturation rate
+    gen = dict(n_streams=n_streams, block_min=64, block_max=1024, n_filters=2 * 1250,
+               submit_threads=args.serve_threads)
     srv.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)          # warm-up
     runs = []
 
@@ -845,6 +846,7 @@ def main():
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
     ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
+    ap.add_argument("--serve-threads", type=int, default=8, help="submitting threads of the load generator")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds per streaming-loop load level (0: skip)")
     ap.add_argument("--no-quality", action="store_true",
