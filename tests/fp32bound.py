@@ -21,3 +21,25 @@ def render_bound(r, src, p, g, t, k):
     mag = oracle.sparse_render_points(np.abs(np.asarray(r, np.float64)), np.abs(np.asarray(src, np.float64)), p,
                                       np.asarray(g, np.float64), t)
     return (len(r) + k + 4) * U32 * mag
+
+
+def moving_bound(r, src, p, g, lg, filt, seg, fade, k):
+    """Per-sample error bound of the FP32 moving render of one ear (filter
+    filt[j] for segment j, a linear crossfade over the first `fade` samples
+    of segments j >= 1).  Outside a crossfade it is render_bound's; inside,
+    y = a y_j + (1 - a) y_{j-1} is formed in FP32 from the two chains' sums
+    (a = (u + 1) / fade rounded, b = (1 - a) y_{j-1} rounded, then one fma),
+    which adds a few roundings of |y_j| + |y_{j-1}|: the bound there is
+    (lf + k + 8) u (m_j + m_{j-1}), m the magnitudes of both filters' hard
+    renders (the oracle's moving render on |r|, |s| with no crossfade)."""
+    r64 = np.abs(np.asarray(r, np.float64))
+    s64 = np.abs(np.asarray(src, np.float64))
+    filt = np.asarray(filt, np.int32)
+    m_cur = oracle.moving_render(r64, s64, p, np.asarray(g, np.float64), lg, filt, seg, 0)
+    prev = np.concatenate([filt[:1], filt[:-1]])
+    m_prev = oracle.moving_render(r64, s64, p, np.asarray(g, np.float64), lg, prev, seg, 0)
+    t = np.arange(m_cur.size)
+    j = t // seg
+    blend = (j >= 1) & (j < filt.size) & (t % seg < fade)
+    c = len(r) + k + 8
+    return c * U32 * (m_cur + np.where(blend, m_prev, 0.0))

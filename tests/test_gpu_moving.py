@@ -7,6 +7,7 @@ relative L2 per (source, ear) row, the bar of every render."""
 import numpy as np
 import pytest
 
+import fp32bound
 import oracle
 import synth
 
@@ -178,6 +179,9 @@ def test_full_size_moving_config(dev):
         for e in range(2):
             ref = oracle.moving_render(r, srcs[s], p, g, lg, seg_filt[s, :, e], seg, fade)
             worst = max(worst, oracle.rel_l2(rows[e, :mv.out_len], ref))
+            # every sample within the FP32 bound of its chains and crossfade
+            bound = fp32bound.moving_bound(r, srcs[s], p, g, lg, seg_filt[s, :, e], seg, fade, k)
+            assert np.all(np.abs(rows[e, :mv.out_len] - ref) <= bound), (s, e)
     assert worst <= TOL, worst
     mv.close()
     plan.close()

@@ -75,3 +75,56 @@ def test_crossfade_weight_is_a_linear_ramp(fade):
     y5 = oracle.sparse_render(r, s, p[5], g[5], LG)
     tt = np.arange(seg, n)
     assert np.max(np.abs(ya[tt] + yb[tt] - y_old[tt] - y5[tt])) <= 1e-12 * np.max(np.abs(y_old))
+
+
+def _fma32(a, b, c):
+    """fl32(a b + c) for FP32 a, b, c (the product is exact in FP64)."""
+    return (np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64)).astype(np.float32)
+
+
+def test_fp32_moving_bound_holds():
+    """The per-sample bound the GPU moving test uses (tests/fp32bound.py):
+    an FP32 emulation of the kernel's arithmetic -- z as a chain of lf fmas,
+    each filter's output as a chain of K fmas in tap order, and inside a
+    crossfade a = (u + 1) / fade, b = (1 - a) y_{j-1}, y = fma(a, y_j, b),
+    all rounded to FP32 -- stays inside it at every sample, and its worst
+    sample comes within a factor of 200 of it."""
+    import fp32bound
+    rng = np.random.default_rng(8)
+    lf, lg, k, nf, seg, fade = 32, 169, 16, 9, 256, 64
+    r = rng.standard_normal(lf).astype(np.float32)
+    s = (rng.standard_normal(2000) * 0.3).astype(np.float32)
+    p, g = synth.random_taps(3, nf, k, lg, nnz_min=k)
+    g = g.astype(np.float32)
+    n_seg = (s.size + seg - 1) // seg
+    filt = rng.integers(0, nf, n_seg).astype(np.int32)
+    L = s.size + lf + lg - 2
+    # z32[u], u < L: chain over the resonance taps
+    z = np.zeros(L, np.float32)
+    for n in range(lf):
+        sh = np.zeros(L, np.float32)
+        sh[n:n + s.size] = s
+        z = _fma32(r[n], sh, z)
+    t = np.arange(L)
+
+    def chain(f):
+        acc = np.zeros(L, np.float32)
+        for q in range(k):
+            zz = np.where(t - p[f, q] >= 0, z[np.clip(t - p[f, q], 0, L - 1)], 0).astype(np.float32)
+            acc = _fma32(g[f, q], zz, acc)
+        return acc
+
+    ys = {f: chain(f) for f in np.unique(filt)}
+    j = np.minimum(t // seg, n_seg - 1)
+    y = np.array([ys[filt[jj]][i] for i, jj in enumerate(j)], np.float32)
+    blend = (t // seg >= 1) & (t // seg < n_seg) & (t % seg < fade)
+    for i in np.nonzero(blend)[0]:
+        u = i % seg
+        a = np.float32(np.float32(u + 1) / np.float32(fade))
+        b = np.float32(np.float32(np.float32(1.0) - a) * ys[filt[j[i] - 1]][i])
+        y[i] = _fma32(a, y[i], b)
+    ref = oracle.moving_render(r, s, p, g.astype(np.float64), lg, filt, seg, fade)
+    bound = fp32bound.moving_bound(r, s, p, g, lg, filt, seg, fade, k)
+    err = np.abs(y.astype(np.float64) - ref)
+    assert np.all(err <= bound)
+    assert np.max(err / np.maximum(bound, 1e-300)) > 0.005
