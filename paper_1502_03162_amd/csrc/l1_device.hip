@@ -31,7 +31,12 @@ namespace {
 
 constexpr int kL1Lanes = 64;
 constexpr int kL1LgMax = 256;
-constexpr int kHsLds = 48;          // passive blocks up to 48 x 48 live in LDS, larger ones in global scratch
+// Passive blocks up to kHsLds x kHsLds live in LDS, larger ones in the
+// workgroup's global scratch.  The LDS of a problem is sized by its lg at
+// launch (six FP64 vectors, two index vectors, this block): at lg = 169 a
+// workgroup takes 18 KB, so 8 fit per CU (a 48 x 48 block and lg-256
+// vectors took 33 KB: 4 per CU, one wave per SIMD).
+constexpr int kHsLds = 32;
 
 struct L1Work {
     double* y;        // current solution
@@ -41,7 +46,7 @@ struct L1Work {
     double* rhs;      // passive right-hand side / solution
     int* passive;
     int* idx;         // passive indices, ascending
-    double* hs_lds;   // kHsLds x kHsLds
+    double* hs_lds;   // kHsLds x kHsLds (LDS)
     double* hs_glb;   // lg x lg global scratch of this workgroup
 };
 
@@ -256,6 +261,12 @@ __device__ int solve_at(const double* __restrict__ H, const double* __restrict__
     return HRIR_OK;
 }
 
+// LDS bytes of a problem of lg = s (the layout at the top of k_l1_solve).
+size_t l1_lds_bytes(int s) {
+    return sizeof(double) * ((size_t)6 * s + kHsLds * kHsLds + kL1Lanes + 1) +
+           sizeof(int) * ((size_t)4 + kL1Lanes + 2 * (size_t)s);
+}
+
 // Problems p = blockIdx.x, blockIdx.x + gridDim.x, ...: problem p uses design
 // H + design[p] * s * s and c0 + p * s; lambda[p] if lambda is given, else the
 // search for at most `target` entries.  Outputs g[p][s], lambda_out[p],
@@ -266,11 +277,20 @@ __global__ __launch_bounds__(kL1Lanes) void k_l1_solve(const double* __restrict_
                                                        double* __restrict__ g_out, double* __restrict__ lambda_out,
                                                        int* __restrict__ nnze_out, int* __restrict__ status,
                                                        double* __restrict__ scratch) {
-    __shared__ double sy[kL1LgMax], sw[kL1LgMax], sz[kL1LgMax], sc[kL1LgMax], srhs[kL1LgMax], sgt[kL1LgMax];
-    __shared__ int spas[kL1LgMax], sidx[kL1LgMax];
-    __shared__ double shs[kHsLds * kHsLds];
-    __shared__ double sh[kL1Lanes + 1];
-    __shared__ int shi[4 + kL1Lanes];
+    // LDS (l1_lds_bytes): y, w, z, c, rhs, gt (s doubles each), the passive
+    // block, the reduction buffers, then passive and idx (s ints each)
+    extern __shared__ double smem[];
+    double* sy = smem;
+    double* sw = sy + s;
+    double* sz = sw + s;
+    double* sc = sz + s;
+    double* srhs = sc + s;
+    double* sgt = srhs + s;
+    double* shs = sgt + s;
+    double* sh = shs + kHsLds * kHsLds;
+    int* shi = reinterpret_cast<int*>(sh + kL1Lanes + 1);
+    int* spas = shi + 4 + kL1Lanes;
+    int* sidx = spas + s;
     L1Work W{sy, sw, sz, sc, srhs, spas, sidx, shs, scratch + (int64_t)blockIdx.x * s * s};
     const int l = threadIdx.x;
     for (int p = blockIdx.x; p < n_prob; p += gridDim.x) {
@@ -328,7 +348,10 @@ int l1_solve_device(const double* H, int n_designs, int s, const double* c0, con
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = std::max(1, std::min(n_prob, 8 * std::max(cus, 1)));
+    const size_t lds = l1_lds_bytes(s);
+    int per_cu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_l1_solve, kL1Lanes, lds);
+    const int grid = std::max(1, std::min(n_prob, std::max(per_cu, 1) * std::max(cus, 1)));
     double *dH = nullptr, *dc = nullptr, *dlam = nullptr, *dg = nullptr, *dlo = nullptr, *dws = nullptr;
     int *dd = nullptr, *dnz = nullptr, *dst = nullptr;
     const size_t ss = (size_t)s * s;
@@ -346,7 +369,7 @@ int l1_solve_device(const double* H, int n_designs, int s, const double* c0, con
     if (e == hipSuccess) e = hipMemcpy(dd, design, sizeof(int) * n_prob, hipMemcpyHostToDevice);
     if (e == hipSuccess && lambda) e = hipMemcpy(dlam, lambda, sizeof(double) * n_prob, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_l1_solve, dim3(grid), dim3(kL1Lanes), 0, nullptr, dH, dc, dd, n_prob, s, dlam, target,
+        hipLaunchKernelGGL(k_l1_solve, dim3(grid), dim3(kL1Lanes), lds, nullptr, dH, dc, dd, n_prob, s, dlam, target,
                            thresh, dg, dlo, dnz, dst, dws);
         e = hipGetLastError();
     }
