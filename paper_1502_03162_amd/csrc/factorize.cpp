@@ -171,25 +171,38 @@ double residual_energy_row(const double* x, int m, const double* f, int lf, cons
 
 // Lawson-Hanson active set on the normal equations: min 1/2 y^T H y - c^T y,
 // y >= 0, with H = A^T A (s x s) and c = A^T x.
-int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y) {
+int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y, bool warm) {
     std::vector<char> passive(s, 0);
     std::vector<double> w(s), z(s), Hs, rhs;
     std::vector<int> idx;
     double cmax = 0.0;
     for (int j = 0; j < s; ++j) cmax = std::max(cmax, std::fabs(c[j]));
     const double tol = 1e-12 * cmax;
-    for (int j = 0; j < s; ++j) y[j] = 0.0;
-    for (int outer = 0; outer < 3 * s + 10; ++outer) {
-        for (int j = 0; j < s; ++j) {
-            double v = c[j];
-            for (int q = 0; q < s; ++q) v -= H[(size_t)j * s + q] * y[q];
-            w[j] = v;
+    // a warm start keeps y (>= 0) and takes its support as the passive set;
+    // the first step then solves on that set before any entry is added
+    bool solve_first = false;
+    for (int j = 0; j < s; ++j) {
+        if (warm && y[j] > 0.0) {
+            passive[j] = 1;
+            solve_first = true;
+        } else {
+            y[j] = 0.0;
         }
-        int best = -1;
-        for (int j = 0; j < s; ++j)
-            if (!passive[j] && w[j] > tol && (best < 0 || w[j] > w[best])) best = j;
-        if (best < 0) break;
-        passive[best] = 1;
+    }
+    for (int outer = 0; outer < 3 * s + 10; ++outer) {
+        if (!solve_first) {
+            for (int j = 0; j < s; ++j) {
+                double v = c[j];
+                for (int q = 0; q < s; ++q) v -= H[(size_t)j * s + q] * y[q];
+                w[j] = v;
+            }
+            int best = -1;
+            for (int j = 0; j < s; ++j)
+                if (!passive[j] && w[j] > tol && (best < 0 || w[j] > w[best])) best = j;
+            if (best < 0) break;
+            passive[best] = 1;
+        }
+        solve_first = false;
         for (int inner = 0; inner <= s + 1; ++inner) {
             idx.clear();
             for (int j = 0; j < s; ++j)

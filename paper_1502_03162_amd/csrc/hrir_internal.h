@@ -44,7 +44,9 @@ int l1_solve_device(const double* H, int n_designs, int s, const double* c0, con
 
 // Lawson-Hanson active-set solution of min 1/2 y^T H y - c^T y over y >= 0,
 // H the s x s normal matrix.  Status code as in hrir.h.
-int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y);
+// warm: start from y (entries > 0 form the passive set) instead of zero;
+// the result is the same minimiser, reached in fewer steps from a nearby one.
+int nnls_normal(const std::vector<double>& H, const std::vector<double>& c, int s, double* y, bool warm = false);
 
 // Runs body(i) for i in [0, n) on up to hardware_concurrency threads with
 // static contiguous chunks.  Results must not depend on the thread count:

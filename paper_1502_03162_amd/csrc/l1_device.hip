@@ -109,60 +109,68 @@ __device__ int chol_solve_wave(double* A, int np, double* rhs, int* shi) {
 }
 
 // Lawson-Hanson active set on the normal equations; returns 0 or ENOTPD.
-// Same steps as nnls_normal() in factorize.cpp.
-__device__ int nnls_wave(const double* __restrict__ H, int s, L1Work& W, double* sh, int* shi) {
+// Same steps as nnls_normal() in factorize.cpp, including its warm start
+// (W.y kept, its entries > 0 the passive set, which is solved on first).
+__device__ int nnls_wave(const double* __restrict__ H, int s, L1Work& W, double* sh, int* shi, bool warm) {
     const int l = threadIdx.x;
     double cm = 0.0;
     for (int j = l; j < s; j += kL1Lanes) cm = fmax(cm, fabs(W.c[j]));
     const double tol = 1e-12 * red_max(cm, sh);
+    int on = 0;
     for (int j = l; j < s; j += kL1Lanes) {
-        W.y[j] = 0.0;
-        W.passive[j] = 0;
+        const bool keep = warm && W.y[j] > 0.0;
+        W.passive[j] = keep ? 1 : 0;
+        if (!keep) W.y[j] = 0.0;
+        on |= keep ? 1 : 0;
     }
+    bool solve_first = __any(on);
     if (l == 0) shi[1] = 0;
     __syncthreads();
     for (int outer = 0; outer < 3 * s + 10; ++outer) {
-        // w = c - H y, each entry's terms in increasing q; y is zero outside
-        // the passive set (idx, from the last inner step) and a zero term
-        // leaves the sum unchanged, so only passive columns are visited
-        const int npv = shi[1];
-        for (int j = l; j < s; j += kL1Lanes) {
-            double v = W.c[j];
-            const double* hr = H + (int64_t)j * s;
-            for (int a = 0; a < npv; ++a) {
-                const int q = W.idx[a];
-                v -= hr[q] * W.y[q];
-            }
-            W.w[j] = v;
-        }
-        // the largest w among the non-passive entries above tol, ties to the
-        // lower index: per lane over its entries in increasing j, then over
-        // the lanes in index order
-        int bj = -1;
-        double bw = 0.0;
-        for (int j = l; j < s; j += kL1Lanes)
-            if (!W.passive[j] && W.w[j] > tol && (bj < 0 || W.w[j] > bw)) {
-                bj = j;
-                bw = W.w[j];
-            }
-        sh[l] = bw;
-        shi[4 + l] = bj;
-        __syncthreads();
-        if (l == 0) {
-            int best = -1;
-            double wb = 0.0;
-            for (int k = 0; k < kL1Lanes; ++k) {
-                const int j = shi[4 + k];
-                if (j >= 0 && (best < 0 || sh[k] > wb || (sh[k] == wb && j < best))) {
-                    best = j;
-                    wb = sh[k];
+        if (!solve_first) {
+            // w = c - H y, each entry's terms in increasing q; y is zero outside
+            // the passive set (idx, from the last inner step) and a zero term
+            // leaves the sum unchanged, so only passive columns are visited
+            const int npv = shi[1];
+            for (int j = l; j < s; j += kL1Lanes) {
+                double v = W.c[j];
+                const double* hr = H + (int64_t)j * s;
+                for (int a = 0; a < npv; ++a) {
+                    const int q = W.idx[a];
+                    v -= hr[q] * W.y[q];
                 }
+                W.w[j] = v;
             }
-            shi[0] = best;
-            if (best >= 0) W.passive[best] = 1;
+            // the largest w among the non-passive entries above tol, ties to the
+            // lower index: per lane over its entries in increasing j, then over
+            // the lanes in index order
+            int bj = -1;
+            double bw = 0.0;
+            for (int j = l; j < s; j += kL1Lanes)
+                if (!W.passive[j] && W.w[j] > tol && (bj < 0 || W.w[j] > bw)) {
+                    bj = j;
+                    bw = W.w[j];
+                }
+            sh[l] = bw;
+            shi[4 + l] = bj;
+            __syncthreads();
+            if (l == 0) {
+                int best = -1;
+                double wb = 0.0;
+                for (int k = 0; k < kL1Lanes; ++k) {
+                    const int j = shi[4 + k];
+                    if (j >= 0 && (best < 0 || sh[k] > wb || (sh[k] == wb && j < best))) {
+                        best = j;
+                        wb = sh[k];
+                    }
+                }
+                shi[0] = best;
+                if (best >= 0) W.passive[best] = 1;
+            }
+            __syncthreads();
+            if (shi[0] < 0) break;
         }
-        __syncthreads();
-        if (shi[0] < 0) break;
+        solve_first = false;
         for (int inner = 0; inner <= s + 1; ++inner) {
             // passive indices in ascending order: a ballot per 64 entries
             int np = 0;
@@ -235,11 +243,11 @@ __device__ int nnls_wave(const double* __restrict__ H, int s, L1Work& W, double*
 
 // One solve at lambda and the discard: g (lds or global, s entries), NNZE.
 __device__ int solve_at(const double* __restrict__ H, const double* __restrict__ c0, int s, double lambda,
-                        double thresh, double* g, L1Work& W, double* sh, int* shi, int* nnze) {
+                        double thresh, double* g, L1Work& W, double* sh, int* shi, int* nnze, bool warm) {
     const int l = threadIdx.x;
     for (int j = l; j < s; j += kL1Lanes) W.c[j] = c0[j] - 0.5 * lambda;
     __syncthreads();
-    const int rc = nnls_wave(H, s, W, sh, shi);
+    const int rc = nnls_wave(H, s, W, sh, shi, warm);
     if (rc) return rc;
     int nz = 0;
     for (int j = l; j < s; j += kL1Lanes) {
@@ -301,10 +309,11 @@ __global__ __launch_bounds__(kL1Lanes) void k_l1_solve(const double* __restrict_
         double lam = 0.0;
         if (lambda) {
             lam = lambda[p];
-            rc = solve_at(Hp, cp, s, lam, thresh, g, W, sh, shi, &nz);
+            rc = solve_at(Hp, cp, s, lam, thresh, g, W, sh, shi, &nz, false);
         } else {
-            // lambda = 0 first; else geometric bisection on [1e-12, 1] * 2 max(c0)
-            rc = solve_at(Hp, cp, s, 0.0, thresh, g, W, sh, shi, &nz);
+            // lambda = 0 first; else geometric bisection on [1e-12, 1] * 2 max(c0),
+            // each step starting from the previous step's minimiser (W.y)
+            rc = solve_at(Hp, cp, s, 0.0, thresh, g, W, sh, shi, &nz, false);
             if (rc == HRIR_OK && nz > target) {
                 double cm = 0.0;
                 for (int j = l; j < s; j += kL1Lanes) cm = fmax(cm, cp[j]);
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(kL1Lanes) void k_l1_solve(const double* __restrict_
                 for (int it = 0; it < 50 && rc == HRIR_OK; ++it) {
                     const double mid = sqrt(lo * hi);
                     int nzm = 0;
-                    rc = solve_at(Hp, cp, s, mid, thresh, sgt, W, sh, shi, &nzm);
+                    rc = solve_at(Hp, cp, s, mid, thresh, sgt, W, sh, shi, &nzm, true);
                     if (rc) break;
                     if (nzm <= target) {
                         hi = mid;

@@ -92,16 +92,18 @@ void design_rhs(const Design& d, const double* x, std::vector<double>& c0) {
         for (int j = 0; j < d.lg; ++j) c0[j] += d.A[(size_t)i * d.lg + j] * b[i];
 }
 
-// One L1-NNLS solve and the discard; returns the status and the NNZE.
+// One L1-NNLS solve into y (warm: starting from y's current contents) and
+// the discard into g; returns the status and the NNZE.
 int solve_one(const Design& d, const std::vector<double>& c0, double lambda, double thresh, std::vector<double>& c,
-              double* g, int* nnze) {
+              std::vector<double>& y, bool warm, double* g, int* nnze) {
     c.resize(d.lg);
+    y.resize(d.lg, 0.0);
     for (int j = 0; j < d.lg; ++j) c[j] = c0[j] - 0.5 * lambda;
-    const int rc = nnls_normal(d.H, c, d.lg, g);
+    const int rc = nnls_normal(d.H, c, d.lg, y.data(), warm);
     if (rc) return rc;
     int nz = 0;
     for (int j = 0; j < d.lg; ++j) {
-        if (std::fabs(g[j]) <= thresh) g[j] = 0.0;
+        g[j] = std::fabs(y[j]) <= thresh ? 0.0 : y[j];
         nz += g[j] != 0.0;
     }
     *nnze = nz;
@@ -112,9 +114,9 @@ int solve_one(const Design& d, const std::vector<double>& c0, double lambda, dou
 // solution keeps at most `target` entries (lambda = 0 if it already does).
 int search_lambda(const Design& d, const std::vector<double>& c0, int target, double thresh, double* g,
                   double* lambda_out, int* nnze_out) {
-    std::vector<double> c, gt(d.lg);
+    std::vector<double> c, y, gt(d.lg);
     int nz = 0;
-    int rc = solve_one(d, c0, 0.0, thresh, c, g, &nz);
+    int rc = solve_one(d, c0, 0.0, thresh, c, y, false, g, &nz);
     if (rc) return rc;
     if (nz <= target) {
         *lambda_out = 0.0;
@@ -128,7 +130,8 @@ int search_lambda(const Design& d, const std::vector<double>& c0, int target, do
     int nz_hi = 0;
     for (int it = 0; it < 50; ++it) {
         const double mid = std::sqrt(lo * hi);
-        rc = solve_one(d, c0, mid, thresh, c, gt.data(), &nz);
+        // each step starts from the previous step's minimiser (unthresholded)
+        rc = solve_one(d, c0, mid, thresh, c, y, true, gt.data(), &nz);
         if (rc) return rc;
         if (nz <= target) {
             hi = mid;
@@ -320,14 +323,14 @@ int sparsify_impl(const double* X, int32_t n, int32_t m, const double* f, int32_
     std::vector<int> status(n, 0);
     hrir::parallel_for(n, [&](int64_t i) {
         const hrir::Design& d = designs[which[i]];
-        std::vector<double> c0, c, g(lg);
+        std::vector<double> c0, c, y, g(lg);
         hrir::design_rhs(d, X + (size_t)i * m, c0);
         double lam = 0.0;
         int nz = 0;
         int st;
         if (lambda) {
             lam = lambda[i];
-            st = hrir::solve_one(d, c0, lam, threshold, c, g.data(), &nz);
+            st = hrir::solve_one(d, c0, lam, threshold, c, y, false, g.data(), &nz);
         } else {
             st = hrir::search_lambda(d, c0, target_nnze, threshold, g.data(), &lam, &nz);
         }
@@ -404,7 +407,7 @@ int tune_sigma_impl(const double* X, int32_t n, int32_t m, const double* f, int3
     std::vector<int> status(n, 0);
     hrir::parallel_for(n, [&](int64_t i) {
         const double* x = X + (size_t)i * m;
-        std::vector<double> c0, c, gh(lg), y(m), mx(m), my(m);
+        std::vector<double> c0, c, yh, gh(lg), y(m), mx(m), my(m);
         dft.floored_magnitude(x, mx.data());
         double best = INFINITY, best_s = grid[0];
         for (int u = 0; u < n_grid; ++u) {
@@ -417,7 +420,7 @@ int tune_sigma_impl(const double* X, int32_t n, int32_t m, const double* f, int3
                 double lam = lambda;
                 const int st = target_nnze > 0
                                    ? hrir::search_lambda(designs[u], c0, target_nnze, threshold, gh.data(), &lam, &nz)
-                                   : hrir::solve_one(designs[u], c0, lambda, threshold, c, gh.data(), &nz);
+                                   : hrir::solve_one(designs[u], c0, lambda, threshold, c, yh, false, gh.data(), &nz);
                 if (st) {
                     status[i] = st;
                     return;
