@@ -58,9 +58,10 @@ def kernel_source_hash(files=QUAD_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str, files=QUAD_SOURCES):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source (else None)."""
+def measured_traffic(name: str, files=QUAD_SOURCES, field: str = "bytes_per_launch"):
+    """HBM bytes per launch (or another field) from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source (else
+    None)."""
     fn = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(fn):
         return None
@@ -70,7 +71,7 @@ def measured_traffic(name: str, files=QUAD_SOURCES):
         return None
     if not d or d.get("source_hash") != kernel_source_hash(files):
         return None
-    return d.get("bytes_per_launch")
+    return d.get(field)
 
 
 def time_launches(fn, steps: int, warmup: int, per_launch=None):
@@ -678,7 +679,8 @@ def bench_surrogate(H, torch, dev, hs, fac, r, lf, lg, args):
            "inference": {"queries": nq, "ms": inf_ms, "queries_per_s": nq / (inf_ms * 1e-3)},
            "moving_render": {"ms_per_step": mms, "output_samples_per_s": n_out / (mms * 1e-3),
                              "algorithmic_GBps": alg / (mms * 1e-3) / 1e9, "algorithmic_bytes": alg,
-                             "traffic_tile_2560": measured_traffic("render_moving", MOVING_SOURCES),
+                             "traffic": measured_traffic("render_moving", MOVING_SOURCES),
+                             "traffic_tile": measured_traffic("render_moving", MOVING_SOURCES, "tile"),
                              "kernel": "k_render_moving<32,16,2>",
                              "tile": best_tile, "ms_by_tile": {str(k): v for k, v in by_tile.items()}}}
     log(f"surrogate inference: {nq} directions in {inf_ms:.3f} ms; fallback {100 * np.mean(choice >= 0):.1f} %; "

@@ -530,13 +530,21 @@ void stream_close(hrir_server* server);
  *                   t - j seg_len < fade with j >= 1, the output is
  *                   a y_j + (1 - a) y_{j-1}, a = (u + 1) / fade, y_j the render
  *                   with segment j's filter.  tile: outputs per workgroup, a
- *                   multiple of 256 up to 4096 (0: 2560).  The plan must
+ *                   multiple of 256 up to 4096 (0: 3072 where three such
+ *                   tiles fit in a CU's LDS, else 2048).  The plan must
  *                   outlive the object.
  * moving_render     seg_filt host i32[n_src][n_seg][2] plan rows (left,
  *                   right) per segment, validated and staged through pinned
- *                   memory (double buffered).  d_out device f32: the row of
- *                   (source i, ear e) at (2 i + e) * out_stride, out_stride >=
- *                   src_len + lf + lg - 2.
+ *                   memory (double buffered) and uploaded on a stream of the
+ *                   object's own, so the upload overlaps the previous
+ *                   call's kernels; the kernels on `stream` wait for it
+ *                   (device events, no host wait).  The render kernel's tap
+ *                   table is formed from the plan's rows (a small kernel on
+ *                   `stream`) by the first call and again by the first call
+ *                   after spconv_plan_topk rewrites rows, so rows predicted
+ *                   on the device before the call are used.  d_out device
+ *                   f32: the row of (source i, ear e) at (2 i + e) *
+ *                   out_stride, out_stride >= src_len + lf + lg - 2.
  * moving_info       host int64[4]: n_seg, output row length, tiles, tile length.
  * Errors: EINVAL, ENOMEM, EDEVICE.
  * ---------------------------------------------------------------------- */

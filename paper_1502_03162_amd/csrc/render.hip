@@ -206,6 +206,7 @@ struct hrir_plan {
     float* d_r = nullptr;   // [n_res][lfp], zero padded
     int* d_p = nullptr;     // [n_filters][kp], padded with (0, 0)
     float* d_g = nullptr;
+    uint64_t rows_gen = 1;    // bumped by every rewrite of tap rows (spconv_plan_topk)
 };
 
 struct hrir_batch {
@@ -379,8 +380,9 @@ extern "C" int spconv_plan(const float* r, int32_t lf, const int32_t* p, const f
 namespace hrir {
 PlanView plan_view(const hrir_plan* pl) {
     return PlanView{pl->lf, pl->lfp, pl->k, pl->kp, pl->lg, pl->n_filters, pl->device, pl->n_res,
-                    pl->d_r, pl->d_p, pl->d_g};
+                    pl->d_r, pl->d_p, pl->d_g, pl->rows_gen};
 }
+void plan_rows_changed(hrir_plan* pl) { ++pl->rows_gen; }
 }  // namespace hrir
 
 extern "C" int spconv_plan_shape(const hrir_plan* plan, int32_t* lf_k_lg3) {

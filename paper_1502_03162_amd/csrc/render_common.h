@@ -175,10 +175,14 @@ struct PlanView {
     float* d_r;
     int* d_p;
     float* d_g;
+    uint64_t rows_gen;      // changes whenever the library rewrites tap rows
 };
 }  // namespace hrir
 struct hrir_plan;
 namespace hrir {
 PlanView plan_view(const hrir_plan* plan);
+// Marks the plan's tap rows as rewritten (called by every library routine
+// that writes them after creation).
+void plan_rows_changed(hrir_plan* plan);
 
 }  // namespace hrir

@@ -14,10 +14,11 @@
 // shifted LDS copies) and work items of NJ x 256 outputs x one ear (NJ quads
 // per lane, 256 outputs apart); seg_len and TB are multiples of NJ x 256, so
 // an item lies inside one segment and only an item that starts a segment
-// blends, over its first quad (fade <= 256).  Taps are staged in LDS as
-// offsets into the quad copies (c CS + H - p - c for position p, c = (H - p)
-// mod 4) with their gains, read 4 at a time, so a tap costs one address add
-// and NJ 16-byte z reads for 4 NJ fmas.
+// blends, over its first `fade` outputs (fade <= 256), one output per lane.
+// Taps come from a table the device forms from the plan's rows before each
+// render (offsets into the quad copies, then gains), read with scalar loads:
+// a tap costs one address add and NJ 16-byte z reads for 4 NJ fmas, with the
+// gain a scalar operand.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,63 +34,67 @@ namespace hrir {
 
 constexpr int kMovItem = 256;     // outputs per work item (one quad per lane)
 
-// Filters a tile can need: both ears of every segment it overlaps and of the
-// segment before (its last samples fade into the tile's first segment).
-__host__ __device__ inline int moving_tile_filters(int TB) { return 2 * (TB / kMovItem + 2); }
-// The filter-row slots, rounded up so the tap arrays after them are 16-byte aligned.
-__host__ __device__ inline int moving_row_slots(int TB) { return (moving_tile_filters(TB) + 3) / 4 * 4; }
-
-// LDS floats after the z copies: filter rows, then their tap offsets and gains.
+// A filter's taps as the kernel reads them: KP offsets into the quad copies
+// (tap position p reads copy c = (H - p) mod 4 at element c CS + H - p - c,
+// where z at output t - p sits for the quad starting at output t), then the
+// KP gains.  Formed on the device for every row of the plan by the first
+// render and again by the first render after the library rewrites rows
+// (spconv_plan_topk), so rows predicted on the device are seen.
 template <int KP>
-__host__ __device__ inline int moving_tap_lds(int TB) {
-    return moving_row_slots(TB) + 2 * KP * moving_tile_filters(TB);
+__global__ __launch_bounds__(256) void k_moving_taps(const int* __restrict__ P, const float* __restrict__ Gv,
+                                                     int n_filters, int H, int CS, int* __restrict__ tbl) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_filters * KP) return;
+    const int f = i / KP, q = i % KP;
+    const int p = P[i];
+    const int c = (H - p) & 3;
+    tbl[f * 2 * KP + q] = c * CS + H - p - c;
+    tbl[f * 2 * KP + KP + q] = __float_as_int(Gv[i]);
 }
 
-// Empty asm over the accumulators that clobbers memory: LDS reads of the
-// next group of taps are not hoisted above it (all of them in flight at once
-// would take 4 VGPRs per tap and read and cost occupancy).  Emits no
-// instruction.
-template <int NJ>
-__device__ __forceinline__ void pin_acc(float (&a)[NJ][4]) {
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj)
-        asm volatile("" : "+v"(a[jj][0]), "+v"(a[jj][1]), "+v"(a[jj][2]), "+v"(a[jj][3]) : : "memory");
+// The tap table as a constant-address-space pointer: loads through it at
+// wave-uniform addresses become scalar loads into SGPRs, so offsets and
+// gains feed the LDS addresses and the fmas as scalar operands, with no
+// LDS staging and no lane-to-scalar moves.  The table and the segment
+// filters do not change while the render kernel runs.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)p;
 }
 
-// offs, gs: one filter's staged taps (LDS offsets into the quad copies and
-// gains; 16-byte aligned, every lane reads the same words).  Taps in groups
-// of 4 (KP is a multiple of 4), accumulated in tap order; the first NJ of
-// the item's quads, 256 outputs apart.
-template <int KP, int NJ, int NA>
-__device__ __forceinline__ void quad_taps(const float* zl, const int* offs, const float* gs, float (&acc)[NA][4]) {
+// acc[jj][i] += g_k z[t - p_k] over the filter's KP taps, in tap order, for
+// this lane's NJ quads (256 outputs apart): one aligned 16-byte LDS read per
+// quad and tap at zo + offset (zo: the lane's first quad).  Taps in groups
+// of 4; the empty asm (no instruction) over the accumulators and zo makes
+// the next group's reads depend on this group's fmas, so they are not all
+// hoisted and in flight at once (4 VGPRs per quad and tap).
+template <int KP, int NJ>
+__device__ __forceinline__ void gather_taps(const float* lds, int zo, cptr<int> T, float (&acc)[NJ][4]) {
     static_assert(KP % 4 == 0, "taps come in groups of 4");
-    static_assert(NJ <= NA, "accumulators for every quad");
+    const cptr<float> G = reinterpret_cast<cptr<float>>(T + KP);
 #pragma unroll
     for (int q0 = 0; q0 < KP; q0 += 4) {
-        const int4 o4 = *reinterpret_cast<const int4*>(offs + q0);
-        const float4 g4 = *reinterpret_cast<const float4*>(gs + q0);
-        // the same words for every lane: keep the taps in scalar registers
-        const int o[4] = {__builtin_amdgcn_readfirstlane(o4.x), __builtin_amdgcn_readfirstlane(o4.y),
-                          __builtin_amdgcn_readfirstlane(o4.z), __builtin_amdgcn_readfirstlane(o4.w)};
-        const float g[4] = {__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.x))),
-                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.y))),
-                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.z))),
-                            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(g4.w)))};
         float4 v[4][NJ];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) v[u][jj] = *reinterpret_cast<const float4*>(zl + o[u] + 256 * jj);
+            for (int jj = 0; jj < NJ; ++jj)
+                v[u][jj] = *reinterpret_cast<const float4*>(lds + zo + T[q0 + u] + 256 * jj);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
-                acc[jj][0] = fmaf(g[u], v[u][jj].x, acc[jj][0]);
-                acc[jj][1] = fmaf(g[u], v[u][jj].y, acc[jj][1]);
-                acc[jj][2] = fmaf(g[u], v[u][jj].z, acc[jj][2]);
-                acc[jj][3] = fmaf(g[u], v[u][jj].w, acc[jj][3]);
+                const float g = G[q0 + u];
+                acc[jj][0] = fmaf(g, v[u][jj].x, acc[jj][0]);
+                acc[jj][1] = fmaf(g, v[u][jj].y, acc[jj][1]);
+                acc[jj][2] = fmaf(g, v[u][jj].z, acc[jj][2]);
+                acc[jj][3] = fmaf(g, v[u][jj].w, acc[jj][3]);
             }
-        pin_acc<NA>(acc);
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj)
+            asm volatile("" : "+v"(acc[jj][0]), "+v"(acc[jj][1]), "+v"(acc[jj][2]), "+v"(acc[jj][3]), "+v"(zo));
     }
 }
 
@@ -98,8 +103,7 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
                                                                 const TileDesc* __restrict__ tiles,
                                                                 const int32_t* __restrict__ seg_filt, int n_seg,
                                                                 int seg_len, int fade, const float* __restrict__ r,
-                                                                const int* __restrict__ P,
-                                                                const float* __restrict__ Gv,
+                                                                const int* __restrict__ taps,
                                                                 float* __restrict__ out, int64_t out_stride, int lg,
                                                                 int TB) {
     constexpr int IL = NJ * kMovItem;                            // outputs per work item
@@ -109,32 +113,9 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
     const int tid = threadIdx.x;
     const int s = td.job_begin;                                  // source index
     const int tile_len = min(TB, td.out_len - td.t0);
-    const int H = lg - 1, CS = quad_cs(TB, H);
-    // The tile's filters: segments j_lo .. j_hi, both ears.  Their rows are
-    // read before the source is staged and their taps copied into LDS while
-    // the source window is ready, so no work item waits on a chain of
-    // global loads (segment -> filter row -> taps).
-    const int j_first = min(td.t0 / seg_len, n_seg - 1);
-    const int j_lo = max(j_first - 1, 0);
-    const int j_hi = min((td.t0 + tile_len - 1) / seg_len, n_seg - 1);
-    const int n_fl = 2 * (j_hi - j_lo + 1);
-    const int64_t row = (int64_t)s * n_seg;
-    int f_mine = 0;
-    if (tid < n_fl) f_mine = seg_filt[(row + j_lo) * 2 + tid];
-    int* lds_f = reinterpret_cast<int*>(lds + lds_quad_len(TB, lg, LFP));
-    int* lds_o = lds_f + moving_row_slots(TB);
-    float* lds_g = reinterpret_cast<float*>(lds_o + moving_tile_filters(TB) * KP);
-    quad_stage<LFP>(td, src, r, lg, TB, lds, tid, [&]() {
-        if (tid < n_fl) lds_f[tid] = f_mine;
-        __syncthreads();
-        for (int a = tid; a < n_fl * KP; a += kQThreads) {
-            const int64_t o = (int64_t)lds_f[a / KP] * KP + a % KP;
-            const int p = P[o];
-            const int c = (H - p) & 3;
-            lds_o[a] = c * CS + (H - p - c);
-            lds_g[a] = Gv[o];
-        }
-    });
+    const cptr<int32_t> sf = as_const(seg_filt) + (int64_t)s * n_seg * 2;
+    const cptr<int> tc = as_const(taps);
+    quad_stage<LFP>(td, src, r, lg, TB, lds, tid);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int n_items = 2 * ((tile_len + IL - 1) / IL);
     for (int it = wave; it < n_items; it += kQWaves) {
@@ -142,26 +123,39 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
         const int t_blk = td.t0 + IL * blk;
         const int j_raw = t_blk / seg_len;
         const int j = min(j_raw, n_seg - 1);
-        const int fi = 2 * (j - j_lo) + e;
-        const float* zl = lds + IL * blk + 4 * lane;
         float acc[NJ][4];
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = acc[jj][1] = acc[jj][2] = acc[jj][3] = 0.0f;
-        quad_taps<KP, NJ>(zl, lds_o + fi * KP, lds_g + fi * KP, acc);
-        if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len && 4 * lane < fade) {
-            // the previous segment's filter over the first quad (fade <= 256),
-            // in the lanes whose outputs blend (the others skip its LDS reads;
-            // the taps are the same words for every lane, so any active lane
-            // gives them to readfirstlane)
-            float acc0[1][4] = {{0.0f, 0.0f, 0.0f, 0.0f}};
-            quad_taps<KP, 1>(zl, lds_o + (fi - 2) * KP, lds_g + (fi - 2) * KP, acc0);
+        gather_taps<KP, NJ>(lds, IL * blk + 4 * lane, tc + (int64_t)sf[2 * j + e] * 2 * KP, acc);
+        if (fade > 0 && j_raw == j && j >= 1 && t_blk == j * seg_len) {
+            // The previous segment's filter over the first `fade` outputs, one
+            // output u per lane: offset o reads element IL blk + u + o, z at
+            // output t_blk + u - p, consecutive lanes on consecutive banks.
+            // Then each value moves to the lane that holds its output: lane
+            // L's outputs 4L + i, i < 4, are output (4L + i) mod 64 of pass
+            // L / 16.  Each output is the fma chain in tap order that the quad
+            // gather forms.
+            const cptr<int> T0 = tc + (int64_t)sf[2 * (j - 1) + e] * 2 * KP;
+            const cptr<float> G0 = reinterpret_cast<cptr<float>>(T0 + KP);
+            float prev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int m = 0; 64 * m < fade; ++m) {
+                const float* zu = lds + IL * blk + 64 * m + lane;
+                float y = 0.0f;
+#pragma unroll
+                for (int q = 0; q < KP; ++q) y = fmaf(G0[q], zu[T0[q]], y);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = __shfl(y, (4 * lane + i) & 63);
+                    if ((lane >> 4) == m) prev[i] = v;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 4 * lane + i;
                 if (u < fade) {
                     // one rounding order in every instantiation: (1 - a) y0, then fma
                     const float a = (float)(u + 1) / (float)fade;
-                    const float b = (1.0f - a) * acc0[0][i];
+                    const float b = (1.0f - a) * prev[i];
                     acc[0][i] = fmaf(a, acc[0][i], b);
                 }
             }
@@ -273,6 +267,7 @@ extern "C" int spconv_plan_topk(hrir_plan* plan, int32_t first_row, const float*
     if (n_rows == 0) return HRIR_OK;
     hipLaunchKernelGGL(k_topk, dim3(n_rows), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), d_dense, row_stride,
                        width, n_rows, pv.k, pv.kp, first_row, pv.d_p, pv.d_g);
+    plan_rows_changed(plan);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "spconv_plan_topk: %s", hipGetErrorString(e));
     return HRIR_OK;
@@ -286,9 +281,18 @@ struct hrir_moving {
     int64_t n_tiles = 0;
     size_t lds = 0;
     TileDesc* d_tiles = nullptr;
+    int* d_taps = nullptr;                        // n_filters x 2 kp: quad-copy offsets, then gains
+    uint64_t taps_gen = 0;                        // the plan's rows_gen the table was formed from
+    hipEvent_t taps_ready = nullptr;              // recorded after the kernel that formed it
     int32_t* d_seg[2] = {nullptr, nullptr};     // double-buffered segment tables
     int32_t* h_seg[2] = {nullptr, nullptr};     // pinned staging
-    hipEvent_t used[2] = {nullptr, nullptr};
+    // The segment table of a call is uploaded on its own stream, so the
+    // upload overlaps the previous call's kernels: copied[b] (copy stream)
+    // orders the kernels after it, read[b] (caller's stream) orders the next
+    // upload into half b after the kernel that reads it.
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t read[2] = {nullptr, nullptr};
     int cur = 0;
 };
 
@@ -297,10 +301,14 @@ namespace {
 void free_moving(hrir_moving* m) {
     if (!m) return;
     (void)hipFree(m->d_tiles);
+    (void)hipFree(m->d_taps);
+    if (m->copy) (void)hipStreamDestroy(m->copy);
+    if (m->taps_ready) (void)hipEventDestroy(m->taps_ready);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(m->d_seg[i]);
         (void)hipHostFree(m->h_seg[i]);
-        if (m->used[i]) (void)hipEventDestroy(m->used[i]);
+        if (m->copied[i]) (void)hipEventDestroy(m->copied[i]);
+        if (m->read[i]) (void)hipEventDestroy(m->read[i]);
     }
     delete m;
 }
@@ -330,7 +338,13 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     if (seg_len < kMovItem || seg_len % kMovItem)
         return fail(HRIR_EINVAL, "moving_create: seg_len=%d must be a positive multiple of %d", seg_len, kMovItem);
     if (fade < 0 || fade > kMovItem) return fail(HRIR_EINVAL, "moving_create: fade=%d outside [0, %d]", fade, kMovItem);
-    if (tile == 0) tile = 2560;     // 2048..4096 measured within 5 % for 2 rows per source
+    if (tile == 0) {
+        // 3,072-sample tiles where three fit in a CU's LDS (counted in 1 KiB
+        // granules), else 2,048 (four per CU, the wave limit): more outputs
+        // resident per CU hide more of each tile's load -> FIR -> gather chain
+        const int l3 = (int)sizeof(float) * lds_quad_len(3072, pv.lg, pv.lfp);
+        tile = 3 * ((l3 + 1023) / 1024 * 1024) <= 160 * 1024 ? 3072 : 2048;
+    }
     if (tile < kMovItem || tile % kMovItem || tile > kQuadTileMax)
         return fail(HRIR_EINVAL, "moving_create: tile=%d must be a multiple of %d in [%d, %d]", tile, kMovItem,
                     kMovItem, kQuadTileMax);
@@ -345,14 +359,7 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     m->nj = (seg_len % (2 * kMovItem) == 0 && tile % (2 * kMovItem) == 0) ? 2 : 1;
     m->n_seg = (int)((src_len + seg_len - 1) / seg_len);
     m->out_len = src_len + pv.lf + pv.lg - 2;
-    const int rc_lds = with_lf_k(pv.lfp, pv.kp, [&](auto, auto K) -> int {
-        m->lds = sizeof(float) * (size_t)(lds_quad_len(m->TB, pv.lg, pv.lfp) + moving_tap_lds<decltype(K)::value>(m->TB));
-        return HRIR_OK;
-    });
-    if (rc_lds) {
-        free_moving(m);
-        return rc_lds;
-    }
+    m->lds = sizeof(float) * (size_t)lds_quad_len(m->TB, pv.lg, pv.lfp);
     std::vector<TileDesc> ht;
     for (int s = 0; s < n_src; ++s)
         for (int64_t t0 = 0; t0 < m->out_len; t0 += m->TB)
@@ -361,12 +368,16 @@ extern "C" int moving_create(const hrir_plan* plan, int32_t n_src, int64_t src_l
     const size_t seg_bytes = sizeof(int32_t) * (size_t)n_src * m->n_seg * 2;
     hipError_t e = m->lds > 160 * 1024 ? hipErrorInvalidValue : hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&m->d_tiles, ht.size() * sizeof(TileDesc));
+    if (e == hipSuccess) e = hipMalloc(&m->d_taps, sizeof(int) * (size_t)pv.n_filters * 2 * pv.kp);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->taps_ready, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_tiles, ht.data(), ht.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipMalloc(&m->d_seg[i], seg_bytes);
         if (e == hipSuccess) e = hipHostMalloc((void**)&m->h_seg[i], seg_bytes, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->used[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->copied[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->read[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) {
         const int rc = with_lf_k(pv.lfp, pv.kp, [&](auto L, auto K) -> int {
@@ -409,27 +420,45 @@ extern "C" int moving_render(hrir_moving* m, const float* d_src, int64_t src_ele
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int b = m->cur;
     m->cur ^= 1;
-    hipError_t e = hipEventSynchronize(m->used[b]);        // the copy that last read this half has run
+    // the upload that last read the pinned half b has finished
+    hipError_t e = hipEventSynchronize(m->copied[b]);
     if (e == hipSuccess) {
         std::memcpy(m->h_seg[b], seg_filt, sizeof(int32_t) * (size_t)n_ent);
-        e = hipMemcpyAsync(m->d_seg[b], m->h_seg[b], sizeof(int32_t) * (size_t)n_ent, hipMemcpyHostToDevice, st);
+        e = hipStreamWaitEvent(m->copy, m->read[b], 0);   // the kernel that last read d_seg[b]
     }
-    if (e == hipSuccess) e = hipEventRecord(m->used[b], st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->d_seg[b], m->h_seg[b], sizeof(int32_t) * (size_t)n_ent, hipMemcpyHostToDevice,
+                           m->copy);
+    if (e == hipSuccess) e = hipEventRecord(m->copied[b], m->copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, m->copied[b], 0);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "moving_render: %s", hipGetErrorString(e));
     int rc = with_lf_k(pv.lfp, pv.kp, [&](auto L, auto K) -> int {
         constexpr int LV = decltype(L)::value, KV = decltype(K)::value;
+        const int H = pv.lg - 1;
+        // the tap table, formed again only when the library has rewritten
+        // the plan's rows since it was last formed
+        if (pv.rows_gen != m->taps_gen) {
+            hipLaunchKernelGGL((k_moving_taps<KV>), dim3((unsigned)((pv.n_filters * KV + 255) / 256)), dim3(256), 0,
+                               st, pv.d_p, pv.d_g, pv.n_filters, H, quad_cs(m->TB, H), m->d_taps);
+            e = hipEventRecord(m->taps_ready, st);
+            if (e == hipSuccess) m->taps_gen = pv.rows_gen;
+        } else {
+            e = hipStreamWaitEvent(st, m->taps_ready, 0);
+        }
+        if (e != hipSuccess) return fail(HRIR_EDEVICE, "moving_render: %s", hipGetErrorString(e));
         if (m->nj == 2)
             hipLaunchKernelGGL((k_render_moving<LV, KV, 2>), dim3((unsigned)m->n_tiles), dim3(kQThreads), m->lds, st,
-                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, pv.d_p, pv.d_g,
+                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, m->d_taps,
                                d_out, out_stride, pv.lg, m->TB);
         else
             hipLaunchKernelGGL((k_render_moving<LV, KV, 1>), dim3((unsigned)m->n_tiles), dim3(kQThreads), m->lds, st,
-                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, pv.d_p, pv.d_g,
+                               d_src, m->d_tiles, m->d_seg[b], m->n_seg, m->seg_len, m->fade, pv.d_r, m->d_taps,
                                d_out, out_stride, pv.lg, m->TB);
         return HRIR_OK;
     });
     if (rc) return rc;
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(m->read[b], st);
     if (e != hipSuccess) return fail(HRIR_EDEVICE, "moving_render: %s", hipGetErrorString(e));
     return HRIR_OK;
 }
