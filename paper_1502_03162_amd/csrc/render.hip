@@ -214,6 +214,7 @@ struct hrir_batch {
     int flags = 0, TB = 0, group = 0, grid = 0;
     int kind = 0;                             // KIND_* below
     int nt = 512;                             // threads per workgroup of the quad kernel
+    bool direct = false;                      // quad kernel: every tile takes the direct stage
     int64_t n_tiles = 0, n_jobs = 0;
     int64_t src_extent = 0, out_extent = 0;   // elements the job list touches
     size_t lds_bytes = 0;
@@ -290,9 +291,9 @@ int launch(hrir_batch* b, const float* d_src, float* d_out, hipStream_t st) {
         });
         if (rc) return rc;
     } else if (b->kind == KIND_QUAD) {
-        int rc = quad_launch(pl->lfp, pl->kp, b->nt, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st,
-                             d_src, b->d_tiles, (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p, pl->d_g, d_out, pl->lg,
-                             b->TB, b->d_ctr);
+        int rc = quad_launch(pl->lfp, pl->kp, b->nt, (b->flags & SPCONV_PERSISTENT) != 0, b->direct, b->grid,
+                             b->lds_bytes, st, d_src, b->d_tiles, (int)b->n_tiles, b->d_jobs, pl->d_r, pl->d_p,
+                             pl->d_g, d_out, pl->lg, b->TB, b->d_ctr);
         if (rc) return rc;
     } else if (b->kind == KIND_REGWIN) {
         int rc = rw_launch(pl->lfp, (b->flags & SPCONV_PERSISTENT) != 0, b->grid, b->lds_bytes, st, d_src, b->d_tiles,
@@ -592,6 +593,7 @@ extern "C" int spconv_batch_create(const hrir_plan* plan, const int64_t* src_off
         return bail(fail(HRIR_EINVAL, "spconv_batch_create: tile %d with lg %d needs %zu B of LDS (> 160 KiB)", tile, lg,
                          b->lds_bytes));
     if (b->n_tiles > INT32_MAX) return bail(fail(HRIR_EINVAL, "spconv_batch_create: too many tiles"));
+    b->direct = quad_direct(ht.data(), (int64_t)ht.size());
     hipError_t e = hipSuccess;
     if (n_jobs > 0) {
         e = hipMalloc(&b->d_tiles, ht.size() * sizeof(TileDesc));
@@ -791,8 +793,8 @@ extern "C" int spconv_render_noalloc(const hrir_plan* plan, const float* d_src, 
         e = hipMemcpyAsync(d_tiles, na_tiles, sizeof(TileDesc) * (size_t)nt, hipMemcpyHostToDevice, st);
     int rc = HRIR_OK;
     if (e == hipSuccess) {
-        rc = quad_launch(plan->lfp, plan->kp, 512, false, grid, lds_bytes, st, d_src, d_tiles, (int)nt, d_jobs,
-                         plan->d_r, plan->d_p, plan->d_g, d_out, lg, tile, nullptr);
+        rc = quad_launch(plan->lfp, plan->kp, 512, false, quad_direct(na_tiles, nt), grid, lds_bytes, st, d_src,
+                         d_tiles, (int)nt, d_jobs, plan->d_r, plan->d_p, plan->d_g, d_out, lg, tile, nullptr);
         if (rc == HRIR_OK) e = hipGetLastError();
     }
     const hipError_t es = hipStreamSynchronize(st);

@@ -164,7 +164,11 @@ int rw_launch(int lfp, bool persistent, int grid, size_t lds_bytes, hipStream_t 
 int quad_lds_bytes(int TB, int lg, int lfp);
 // nt: threads per workgroup, 512 or 256 (256 needs TB + lg + 2 <= 4096).
 int quad_prepare(int lfp, int kp, int nt, size_t lds_bytes, bool persistent, int64_t n_tiles, int* grid);
-int quad_launch(int lfp, int kp, int nt, bool persistent, int grid, size_t lds_bytes, hipStream_t st,
+// True when every tile has fewer jobs than the staging-priority threshold:
+// the one-tile quad kernel then takes the direct stage (the persistent one
+// always does).
+bool quad_direct(const TileDesc* tiles, int64_t n_tiles);
+int quad_launch(int lfp, int kp, int nt, bool persistent, bool direct, int grid, size_t lds_bytes, hipStream_t st,
                 const float* src, const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r,
                 const int* P, const float* Gv, float* out, int lg, int TB, int* ctr);
 constexpr int kQuadTileMax = 4096;

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kQThreads, 4) void k_render_moving(const float* __r
     const int tile_len = min(TB, td.out_len - td.t0);
     const cptr<int32_t> sf = as_const(seg_filt) + (int64_t)s * n_seg * 2;
     const cptr<int> tc = as_const(taps);
-    quad_stage<LFP>(td, src, r, lg, TB, lds, tid);
+    quad_stage_direct<LFP>(td, src, r, lg, TB, lds, tid);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int n_items = 2 * ((tile_len + IL - 1) / IL);
     for (int it = wave; it < n_items; it += kQWaves) {

@@ -33,6 +33,52 @@ __host__ __device__ inline int lds_quad_len(int TB, int lg, int lfp) {
     return s_len > c_len ? s_len : c_len;
 }
 
+// Writes one thread's 8 z values, z_win[u0 .. u0 + 7], into the four
+// shifted copies: Zc[m] = z_win[m + c] for m < mlim; interior groups of 8
+// without tests.
+__device__ __forceinline__ void quad_copies(const float (&zz)[kZpt], int u0, int mlim, int CS, float* zc, int tid) {
+    if (u0 >= 4 && u0 + kZpt <= mlim) {
+        float* z0 = zc + u0;
+        *reinterpret_cast<float4*>(z0) = make_float4(zz[0], zz[1], zz[2], zz[3]);
+        *reinterpret_cast<float4*>(z0 + 4) = make_float4(zz[4], zz[5], zz[6], zz[7]);
+        // Copies 1..3 are not 16-byte aligned: one dword per lane per
+        // store.  Lanes are 8 dwords apart, so if every lane stored the
+        // same element a, 8 lanes would share each bank.  Store k writes
+        // element (k + lane / 8) mod 8 instead, which puts the 64 lanes
+        // on 64 different banks; the lane's values are rotated by
+        // lane / 8 to match: a vector of 8 rotated by 1, 2 and 4 under
+        // the bits of g, 8 selects per stage on one condition.  (On an
+        // array indexed inside a loop the compiler merges the stages into
+        // an 8-way select per value, about five times the instructions.)
+        const int g = (tid >> 3) & 7;
+        f8v zr = {zz[0], zz[1], zz[2], zz[3], zz[4], zz[5], zz[6], zz[7]};
+        if (g & 1) zr = __builtin_shufflevector(zr, zr, 1, 2, 3, 4, 5, 6, 7, 0);
+        if (g & 2) zr = __builtin_shufflevector(zr, zr, 2, 3, 4, 5, 6, 7, 0, 1);
+        if (g & 4) zr = __builtin_shufflevector(zr, zr, 4, 5, 6, 7, 0, 1, 2, 3);
+        // zr[k] = zz[(k + g) mod 8], stored at element (k + g) mod 8.
+        // The element offsets pass through an empty asm (no instruction):
+        // seen through, they let the compiler turn the rotated stores back
+        // into fixed-offset stores of values picked by 8-way selects.
+        int ok[kZpt];
+#pragma unroll
+        for (int k = 0; k < kZpt; ++k) ok[k] = (k + g) & (kZpt - 1);
+        asm volatile("" : "+v"(ok[0]), "+v"(ok[1]), "+v"(ok[2]), "+v"(ok[3]), "+v"(ok[4]), "+v"(ok[5]),
+                          "+v"(ok[6]), "+v"(ok[7]));
+#pragma unroll
+        for (int c = 1; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < kZpt; ++k) zc[c * CS + u0 + ok[k] - c] = zr[k];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int a = 0; a < kZpt; ++a) {
+                const int m = u0 + a - c;
+                if (m >= 0 && m < mlim) zc[c * CS + m] = zz[a];
+            }
+    }
+}
+
 // Stages the tile's source, runs the FIR and writes the four shifted copies
 // of z into lds (ends with a barrier).  H = lg - 1; CS = quad_cs(TB, H).
 // Only the z values the tile's outputs read are formed (a ragged last tile
@@ -96,51 +142,70 @@ __device__ __forceinline__ void quad_stage(const TileDesc& td, const float* __re
         }
     }
     __syncthreads();                            // every read of s_win is done
-    // Zc[m] = z_win[m + c] for m < tile_len + H; interior groups of 8 without tests
+    // Zc[m] = z_win[m + c] for m < tile_len + H
     const int mlim = tile_len + H;
 #pragma unroll
     for (int ps = 0; ps < kQPass; ++ps) {
         const int u0 = (ps * NT + tid) * kZpt;
-        if (u0 >= 4 && u0 + kZpt <= mlim) {
-            float* z0 = zc + u0;
-            *reinterpret_cast<float4*>(z0) = make_float4(zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3]);
-            *reinterpret_cast<float4*>(z0 + 4) = make_float4(zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]);
-            // Copies 1..3 are not 16-byte aligned: one dword per lane per
-            // store.  Lanes are 8 dwords apart, so if every lane stored the
-            // same element a, 8 lanes would share each bank.  Store k writes
-            // element (k + lane / 8) mod 8 instead, which puts the 64 lanes
-            // on 64 different banks; the lane's values are rotated by
-            // lane / 8 to match: a vector of 8 rotated by 1, 2 and 4 under
-            // the bits of g, 8 selects per stage on one condition.  (On an
-            // array indexed inside a loop the compiler merges the stages into
-            // an 8-way select per value, about five times the instructions.)
-            const int g = (tid >> 3) & 7;
-            f8v zr = {zz[ps][0], zz[ps][1], zz[ps][2], zz[ps][3], zz[ps][4], zz[ps][5], zz[ps][6], zz[ps][7]};
-            if (g & 1) zr = __builtin_shufflevector(zr, zr, 1, 2, 3, 4, 5, 6, 7, 0);
-            if (g & 2) zr = __builtin_shufflevector(zr, zr, 2, 3, 4, 5, 6, 7, 0, 1);
-            if (g & 4) zr = __builtin_shufflevector(zr, zr, 4, 5, 6, 7, 0, 1, 2, 3);
-            // zr[k] = zz[ps][(k + g) mod 8], stored at element (k + g) mod 8.
-            // The element offsets pass through an empty asm (no instruction):
-            // seen through, they let the compiler turn the rotated stores back
-            // into fixed-offset stores of values picked by 8-way selects.
-            int ok[kZpt];
+        if (u0 < nz8) quad_copies(zz[ps], u0, mlim, CS, zc, tid);
+    }
+    __syncthreads();
+}
+
+// The same z tile with no source window in LDS: each thread reads its FIR
+// window (LFP + 7 samples for its 8 z values) straight from global memory,
+// where neighbouring threads' windows overlap in the vector cache, and
+// writes its z values into the copies at once, so a tile takes one barrier
+// instead of three.  The z values are quad_stage's, bit for bit (same
+// windows, same fma order).  In a loop over tiles the caller's barrier
+// after the previous tile's gather must precede it (the copies are written
+// without one).
+template <int LFP, int NT = kQThreads>
+__device__ __forceinline__ void quad_stage_direct(const TileDesc& td, const float* __restrict__ src,
+                                                  const float* __restrict__ r, int lg, int TB, float* zc, int tid,
+                                                  bool prio = false) {
+    static_assert(NT == 512 || NT == 256, "quad workgroups have 256 or 512 threads");
+    const int H = lg - 1;
+    const int tile_len = min(TB, td.out_len - td.t0);
+    const int nz8 = round_up(tile_len + H + 3, kZpt);
+    const int CS = quad_cs(TB, H);
+    const int mlim = tile_len + H;
+    // window sample i of z_win[u0] is source sample sbase + u0 + i
+    const int64_t sbase = (int64_t)td.t0 - H - (LFP - 1);
+    const float* sp = src + td.src_off;
+    const bool interior = sbase >= 0 && sbase + nz8 + LFP <= td.src_len;
+    float rr[LFP];
 #pragma unroll
-            for (int k = 0; k < kZpt; ++k) ok[k] = (k + g) & (kZpt - 1);
-            asm volatile("" : "+v"(ok[0]), "+v"(ok[1]), "+v"(ok[2]), "+v"(ok[3]), "+v"(ok[4]), "+v"(ok[5]),
-                              "+v"(ok[6]), "+v"(ok[7]));
+    for (int n = 0; n < LFP; ++n) rr[n] = r[n];
 #pragma unroll
-            for (int c = 1; c < 4; ++c)
+    for (int ps = 0; ps < kQPass; ++ps) {
+        const int u0 = (ps * NT + tid) * kZpt;
+        if (u0 >= nz8) continue;
+        float w[LFP + kZpt];
+        if (prio) __builtin_amdgcn_s_setprio(2);
+        if (interior) {
 #pragma unroll
-                for (int k = 0; k < kZpt; ++k) zc[c * CS + u0 + ok[k] - c] = zr[k];
-        } else if (u0 < nz8) {
+            for (int i = 0; i < LFP + kZpt; i += 4) {
+                const f4u x = *reinterpret_cast<const f4u*>(sp + sbase + u0 + i);
+                w[i] = x.x; w[i + 1] = x.y; w[i + 2] = x.z; w[i + 3] = x.w;
+            }
+        } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int a = 0; a < kZpt; ++a) {
-                    const int m = u0 + a - c;
-                    if (m >= 0 && m < mlim) zc[c * CS + m] = zz[ps][a];
-                }
+            for (int i = 0; i < LFP + kZpt; ++i) {
+                const int64_t q = sbase + u0 + i;
+                w[i] = (q >= 0 && q < td.src_len) ? sp[q] : 0.0f;
+            }
         }
+        if (prio) __builtin_amdgcn_s_setprio(0);
+        float zz[kZpt];
+#pragma unroll
+        for (int a = 0; a < kZpt; ++a) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int n = 0; n < LFP; ++n) acc = fmaf(rr[n], w[a + LFP - 1 - n], acc);
+            zz[a] = acc;
+        }
+        quad_copies(zz, u0, mlim, CS, zc, tid);
     }
     __syncthreads();
 }

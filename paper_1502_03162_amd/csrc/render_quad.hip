@@ -34,15 +34,28 @@ namespace hrir {
 
 // Tiles with at least this many jobs stage their source at raised wave
 // priority (measured: 2-3 % faster at 40 jobs per tile, slower at 1..16).
+// A batch whose tiles all have fewer jobs runs the direct stage instead
+// (FIR windows read from global memory, one barrier per tile instead of
+// three): measured 3-5 % faster on the uneven workload and 2 % slower at 40
+// jobs per tile, where its extra vector-memory loads compete with the
+// tile's 40 row stores.
 constexpr int kQPrioJobs = 24;
 
-template <int LFP, int KP, int NT>
+// DIRECT: the tile reads its FIR windows from global memory
+// (quad_stage_direct); otherwise it stages the source window in LDS
+// (quad_stage), at raised priority with at least kQPrioJobs jobs.
+template <int LFP, int KP, int NT, bool DIRECT>
 __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float* __restrict__ src,
                                                  const JobDesc* __restrict__ jobs, const float* __restrict__ r,
                                                  const int* __restrict__ P, const float* __restrict__ Gv,
                                                  float* __restrict__ out, int lg, int TB, float* lds, int tid) {
     constexpr int kWv = NT / 64;
-    quad_stage<LFP, NT>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid, NoHook{}, td.job_count >= kQPrioJobs);
+    // both stages form the same z, bit for bit
+    if (DIRECT)
+        quad_stage_direct<LFP, NT>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid);
+    else
+        quad_stage<LFP, NT>(td, src, r + (int64_t)td.res * LFP, lg, TB, lds, tid, NoHook{},
+                            td.job_count >= kQPrioJobs);
     const int H = lg - 1;
     const int CS = quad_cs(TB, H);
     const float* zc = lds;
@@ -131,10 +144,11 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
     }
 }
 
-// 512-thread workgroups take 4 per CU (LDS at the default tile); 256-thread
-// ones are held to 64 VGPRs so that 8 fit (32 waves per CU).
-template <int LFP, int KP, int NT>
-__global__ __launch_bounds__(NT, NT == 512 ? 4 : 8) void k_render_quad(const float* __restrict__ src,
+// Held to 64 VGPRs (8 waves per SIMD) for lf <= 32, so that 4 workgroups of
+// 512 threads (LDS at the default tile) or 8 of 256 fit per CU; for longer
+// resonance filters 512-thread workgroups may take more registers.
+template <int LFP, int KP, int NT, bool DIRECT>
+__global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render_quad(const float* __restrict__ src,
                                                                      const TileDesc* __restrict__ tiles,
                                                                      const JobDesc* __restrict__ jobs,
                                                                      const float* __restrict__ r,
@@ -143,14 +157,17 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 8) void k_render_quad(const flo
                                                                      float* __restrict__ out, int lg, int TB) {
     extern __shared__ float4 smem4[];
     const TileDesc td = tiles[blockIdx.x];
-    render_tile_quad<LFP, KP, NT>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4),
+    render_tile_quad<LFP, KP, NT, DIRECT>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4),
                                   (int)threadIdx.x);
 }
 
 // Persistent variant over the device tile counter (see k_render_persistent).
 // For lf <= 32 it is held to 64 VGPRs (8 waves per SIMD, 4 tiles per CU like
-// the one-tile kernel) at the cost of a few spilled dwords per lane; with
-// 73 VGPRs it would fit 3 tiles per CU, and the loop measured 2-5 % slower.
+// the one-tile kernel), which costs a few spilled dwords per lane at some
+// tap counts (none at K = 16); with 73 VGPRs it would fit 3 tiles per CU,
+// and the loop measured 2-5 % slower.  Its tiles always take the direct
+// stage: with both stages in the loop it spilled more and measured 2-6 %
+// slower.
 template <int LFP, int KP, int NT>
 __global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render_quad_persistent(
     const float* __restrict__ src, const TileDesc* __restrict__ tiles, int n_tiles,
@@ -173,7 +190,7 @@ __global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render
         const int tid = (int)threadIdx.x + zero;
         const int z = __builtin_amdgcn_readfirstlane(zero);
         const TileDesc td = tiles[t];
-        render_tile_quad<LFP, KP, NT>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
+        render_tile_quad<LFP, KP, NT, true>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
                                   reinterpret_cast<float*>(smem4), tid);
         __syncthreads();
     }
@@ -211,9 +228,11 @@ int quad_prepare(int lfp, int kp, int nt, size_t lds_bytes, bool persistent, int
     return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
         return with_nt(nt, [&](auto N) -> int {
             constexpr int LV = decltype(L)::value, KV = decltype(K)::value, NV = decltype(N)::value;
-            const void* kt = reinterpret_cast<const void*>(&k_render_quad<LV, KV, NV>);
+            const void* kt = reinterpret_cast<const void*>(&k_render_quad<LV, KV, NV, false>);
+            const void* kd = reinterpret_cast<const void*>(&k_render_quad<LV, KV, NV, true>);
             const void* kpers = reinterpret_cast<const void*>(&k_render_quad_persistent<LV, KV, NV>);
             hipError_t e = hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e == hipSuccess) e = hipFuncSetAttribute(kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
             if (e == hipSuccess)
                 e = hipFuncSetAttribute(kpers, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
             if (e != hipSuccess) return fail(HRIR_EDEVICE, "quad_prepare: %s", hipGetErrorString(e));
@@ -232,7 +251,13 @@ int quad_prepare(int lfp, int kp, int nt, size_t lds_bytes, bool persistent, int
     });
 }
 
-int quad_launch(int lfp, int kp, int nt, bool persistent, int grid, size_t lds_bytes, hipStream_t st,
+bool quad_direct(const TileDesc* tiles, int64_t n_tiles) {
+    for (int64_t i = 0; i < n_tiles; ++i)
+        if (tiles[i].job_count >= kQPrioJobs) return false;
+    return true;
+}
+
+int quad_launch(int lfp, int kp, int nt, bool persistent, bool direct, int grid, size_t lds_bytes, hipStream_t st,
                 const float* src, const TileDesc* tiles, int n_tiles, const JobDesc* jobs, const float* r,
                 const int* P, const float* Gv, float* out, int lg, int TB, int* ctr) {
     return with_lf_k(lfp, kp, [&](auto L, auto K) -> int {
@@ -241,9 +266,12 @@ int quad_launch(int lfp, int kp, int nt, bool persistent, int grid, size_t lds_b
             if (persistent)
                 hipLaunchKernelGGL((k_render_quad_persistent<LV, KV, NV>), dim3(grid), dim3(NV), lds_bytes, st, src,
                                    tiles, n_tiles, jobs, r, P, Gv, out, lg, TB, ctr);
+            else if (direct)
+                hipLaunchKernelGGL((k_render_quad<LV, KV, NV, true>), dim3((unsigned)n_tiles), dim3(NV), lds_bytes,
+                                   st, src, tiles, jobs, r, P, Gv, out, lg, TB);
             else
-                hipLaunchKernelGGL((k_render_quad<LV, KV, NV>), dim3((unsigned)n_tiles), dim3(NV), lds_bytes, st,
-                                   src, tiles, jobs, r, P, Gv, out, lg, TB);
+                hipLaunchKernelGGL((k_render_quad<LV, KV, NV, false>), dim3((unsigned)n_tiles), dim3(NV), lds_bytes,
+                                   st, src, tiles, jobs, r, P, Gv, out, lg, TB);
             return HRIR_OK;
         });
     });

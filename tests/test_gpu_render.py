@@ -169,6 +169,32 @@ def test_launch_variants_bitwise_identical(dev):
             assert np.array_equal(a, b), v
 
 
+def test_lds_and_direct_stages_bitwise_identical(dev):
+    """Tiles with many jobs stage the source window in LDS; batches whose
+    tiles all have few jobs, and the persistent kernel, read the FIR windows
+    from global memory.  Both form the same z, so the rows agree bit for bit
+    (30 jobs per source: the one-tile kernel takes the LDS stage; group=3 and
+    the persistent launch take the direct one), also at sources shorter than
+    a tile and on tiles that reach past either end of the source."""
+    h = H()
+    rng = np.random.default_rng(5)
+    lf, lg, k, F = 32, 169, 16, 40
+    r = rng.standard_normal(lf).astype(np.float32)
+    p, g = synth.random_taps(6, F, k, lg, nnz_min=4)
+    lens = [9000, 100, 5000]
+    srcs = [synth.pink(300 + i, n) for i, n in enumerate(lens)]
+    jobs = [(i, (7 * i + j) % F) for i in range(len(lens)) for j in range(30)]
+    plan = h.Plan(r, p, g, lg)
+    base = render_rows(plan, srcs, jobs, dev)
+    check(base, oracle_rows(r, srcs, p, g, lg, jobs))
+    PS, W = h.SPCONV_PERSISTENT, h.SPCONV_WG256
+    for v in (dict(group=3), dict(flags=PS), dict(group=3, flags=PS), dict(flags=W, group=3), dict(tile=1024)):
+        rows = render_rows(plan, srcs, jobs, dev, **v)
+        for a, b in zip(rows, base):
+            assert np.array_equal(a, b), v
+    plan.close()
+
+
 def test_graph_replays_match_eager(dev):
     import torch
     h = H()
