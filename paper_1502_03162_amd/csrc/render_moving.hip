@@ -15,10 +15,11 @@
 // per lane, 256 outputs apart); seg_len and TB are multiples of NJ x 256, so
 // an item lies inside one segment and only an item that starts a segment
 // blends, over its first `fade` outputs (fade <= 256), one output per lane.
-// Taps come from a table the device forms from the plan's rows before each
-// render (offsets into the quad copies, then gains), read with scalar loads:
-// a tap costs one address add and NJ 16-byte z reads for 4 NJ fmas, with the
-// gain a scalar operand.
+// Taps come from a table the device forms from the plan's rows (offsets into
+// the quad copies, then gains; formed again after the library rewrites
+// rows), read with scalar loads: a tap costs one address add and NJ 16-byte
+// z reads for 4 NJ fmas, with the gain a scalar operand.  z is formed by the
+// direct stage (FIR windows read from global memory, one barrier).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,6 +1,7 @@
 // The z tile of the quad LDS-gather kernels (render_quad.hip,
-// render_moving.hip): the source window is staged in LDS, the resonance FIR
-// forms z in registers, and z is written back as four copies shifted by
+// render_moving.hip): the resonance FIR forms z in registers, from a source
+// window staged in LDS (quad_stage) or read by each thread from global
+// memory (quad_stage_direct), and z is written as four copies shifted by
 // 0..3 samples, Zc[m] = z[t0 - H + m + c], so that every tap of every quad of
 // outputs is one aligned 16-byte LDS read.
 #pragma once

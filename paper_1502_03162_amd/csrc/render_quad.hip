@@ -148,17 +148,14 @@ __device__ __forceinline__ void render_tile_quad(const TileDesc& td, const float
 // 512 threads (LDS at the default tile) or 8 of 256 fit per CU; for longer
 // resonance filters 512-thread workgroups may take more registers.
 template <int LFP, int KP, int NT, bool DIRECT>
-__global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render_quad(const float* __restrict__ src,
-                                                                     const TileDesc* __restrict__ tiles,
-                                                                     const JobDesc* __restrict__ jobs,
-                                                                     const float* __restrict__ r,
-                                                                     const int* __restrict__ P,
-                                                                     const float* __restrict__ Gv,
-                                                                     float* __restrict__ out, int lg, int TB) {
+__global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render_quad(
+    const float* __restrict__ src, const TileDesc* __restrict__ tiles, const JobDesc* __restrict__ jobs,
+    const float* __restrict__ r, const int* __restrict__ P, const float* __restrict__ Gv, float* __restrict__ out,
+    int lg, int TB) {
     extern __shared__ float4 smem4[];
     const TileDesc td = tiles[blockIdx.x];
     render_tile_quad<LFP, KP, NT, DIRECT>(td, src, jobs, r, P, Gv, out, lg, TB, reinterpret_cast<float*>(smem4),
-                                  (int)threadIdx.x);
+                                          (int)threadIdx.x);
 }
 
 // Persistent variant over the device tile counter (see k_render_persistent).
@@ -191,7 +188,7 @@ __global__ __launch_bounds__(NT, (LFP <= 32 || NT == 256) ? 8 : 4) void k_render
         const int z = __builtin_amdgcn_readfirstlane(zero);
         const TileDesc td = tiles[t];
         render_tile_quad<LFP, KP, NT, true>(td, src + z, jobs + z, r + z, P + z, Gv + z, out + z, lg + z, TB + z,
-                                  reinterpret_cast<float*>(smem4), tid);
+                                            reinterpret_cast<float*>(smem4), tid);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
