@@ -188,6 +188,29 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
         f"{'256' if best['flags'] & H.SPCONV_WG256 else '512'} threads (autotune {tune_s:.1f} s); best shape of any "
         f"launch form {free_ms:.3f} ms (tile {free_best['tile']}, group {free_best['group']}, flags "
         f"{free_best['flags']})")
+    forms = None
+    if args.uneven_forms > 0:
+        # The persistent shape against the same shape as a plain grid, no
+        # graph: 20 warm-up launches of the plain grid and 10 of the
+        # persistent launch, then alternating blocks of 10 launches (a
+        # counter or trace run takes each form's last 10 * uneven_forms).
+        shape_flags = best["flags"] & ~(H.SPCONV_PERSISTENT | H.SPCONV_GRAPH)
+        bp = H.Batch(plan, off, lens, rows, tile=best["tile"], group=best["group"], flags=shape_flags)
+        bs = H.Batch(plan, off, lens, rows, tile=best["tile"], group=best["group"],
+                     flags=shape_flags | H.SPCONV_PERSISTENT)
+        for b, n in ((bp, 20), (bs, 10)):
+            for _ in range(n):
+                b.render(src, out)
+        torch.cuda.synchronize()
+        t_p, t_s = [], []
+        for _ in range(args.uneven_forms):
+            t_p.append(time_launches(lambda: bp.render(src, out), 10, 0)[0])
+            t_s.append(time_launches(lambda: bs.render(src, out), 10, 0)[0])
+        bp.close()
+        bs.close()
+        forms = {"plain_ms": float(np.mean(t_p)), "persistent_ms": float(np.mean(t_s)),
+                 "blocks": args.uneven_forms, "note": "same shape, no graph, alternating blocks of 10 launches"}
+        log(f"uneven forms: plain {forms['plain_ms']:.3f} ms, persistent {forms['persistent_ms']:.3f} ms")
     del out, src
     torch.cuda.empty_cache()
     return {"workload": "512 pink sources, lengths log-uniform in [4096, 1048576], 1..8 directions x 2 ears, K=16, "
@@ -201,7 +224,8 @@ def bench_uneven(H, torch, dev, fac, r, lf, lg, args):
             "best_any_shape": {"tile": free_best["tile"], "group": free_best["group"],
                                "persistent": bool(free_best["flags"] & H.SPCONV_PERSISTENT),
                                "threads_per_workgroup": 256 if free_best["flags"] & H.SPCONV_WG256 else 512,
-                               "ms_per_step": free_ms, "autotune_ms": free_best["ms"]}}
+                               "ms_per_step": free_ms, "autotune_ms": free_best["ms"]},
+            "forms": forms}
 
 
 def bench_latency(H, torch, dev, fac, r, lg, args):
@@ -847,6 +871,9 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--fft-sizes", default="1024,4096,16384")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
+    ap.add_argument("--uneven-forms", type=int, default=0,
+                    help="also time the persistent shape against the same shape as a plain grid (no graph), "
+                         "this many alternating blocks of 10 launches each")
     ap.add_argument("--latency-ticks", type=int, default=10000, help="block-render launches timed (0: skip)")
     ap.add_argument("--serve-threads", type=int, default=8, help="submitting threads of the load generator")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
