@@ -346,7 +346,9 @@ def bench_serving(H, fac, r, lg, args):
                         "generator_limited": med["generator_limited"], "saturated": med["saturated"]}
         p99s = ", ".join("%.0f" % (st["p99_ms"] * 1e3) for st in reps)
         note(f"serving {label}: median run p99 {med['p99_ms'] * 1e3:.0f} us (runs {p99s} us)")
+    cpu0, wall0 = time.process_time(), time.perf_counter()
     rt = run("real time", rt_hz, 9)
+    rt_cpu = (time.process_time() - cpu0) / (time.perf_counter() - wall0)
     info = srv.info()
     srv.close()
     direct = H.Server(plan, n_streams, hbm_budget=1 << 30, flags=H.STREAM_DIRECT_LAUNCH)
@@ -366,6 +368,20 @@ def bench_serving(H, fac, r, lg, args):
              "real time": zc.loadgen(sig, rate_hz=rt_hz, duration_s=secs, seed=9, **gen)}
     zruns["load 40%"] = zc.loadgen(sig, rate_hz=0.4 * sat_hz, duration_s=secs, seed=3, **gen)
     zc.close()
+    # the completion thread asleep on blocking-sync events: host CPU time per
+    # second of the real-time run (the generator's threads included in both)
+    sl = H.Server(plan, n_streams, hbm_budget=1 << 30, flags=H.STREAM_SLEEPING_COMPLETION)
+    sl.loadgen(sig, rate_hz=0, duration_s=0.2, seed=1, **gen)
+    cpu0, wall0 = time.process_time(), time.perf_counter()
+    srt = sl.loadgen(sig, rate_hz=rt_hz, duration_s=secs, seed=9, **gen)
+    sl_cpu = (time.process_time() - cpu0) / (time.perf_counter() - wall0)
+    ssat = sl.loadgen(sig, rate_hz=0, duration_s=secs, seed=2, **gen)
+    sl.close()
+    sleeping = {"real_time_p50_ms": srt["p50_ms"], "real_time_p99_ms": srt["p99_ms"],
+                "real_time_host_cpu_per_s": sl_cpu, "polling_real_time_host_cpu_per_s": rt_cpu,
+                "saturation_blocks_per_s": ssat["achieved_hz"]}
+    note(f"serving sleeping completion: real time p50/p99 {srt['p50_ms'] * 1e3:.0f}/{srt['p99_ms'] * 1e3:.0f} us, "
+         f"host CPU {sl_cpu:.2f} s/s against {rt_cpu:.2f} s/s polling; saturation {ssat['achieved_hz']:.4g} blocks/s")
     plan.close()
     for label, st in zruns.items():
         st["label"] = label
@@ -378,6 +394,7 @@ def bench_serving(H, fac, r, lg, args):
             "saturation_x_realtime": sat_hz / rt_hz, "p50_ms_realtime": rt["p50_ms"], "p99_ms_realtime": rt["p99_ms"],
             "generations": info["generations"], "gen_samples": info["gen_samples"],
             "load_sweep": sweep, "runs": runs, "direct_launch_saturation_blocks_per_s": dsat["achieved_hz"],
+            "sleeping_completion": sleeping,
             "zero_copy_runs": list(zruns.values()),
             "load_definition": "offered block rate / measured saturation rate of the loop"}
 

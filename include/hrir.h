@@ -446,7 +446,12 @@ void block_streams_destroy(hrir_streams* streams);
  *                input blocks, outputs) in pinned, coherent host memory
  *                that the kernel reads and writes in place -- a launch needs
  *                no copy commands, and hbm_budget then bounds the
- *                histories plus that pinned ring.  Starts a loop thread and
+ *                histories plus that pinned ring; STREAM_SLEEPING_COMPLETION
+ *                makes the completion thread wait for each generation in
+ *                the driver (a blocking-sync event: the thread sleeps
+ *                until the GPU signals) instead of polling the event with
+ *                pauses, which frees a host core for other servers at the
+ *                cost of the wake-up latency.  Starts a loop thread and
  *                a completion thread on the current device.
  * stream_submit  copies n samples (1..4096) of host_block; the caller keeps
  *                its buffer.  filt_l/filt_r are the block's left/right
@@ -483,6 +488,7 @@ void block_streams_destroy(hrir_streams* streams);
  * ---------------------------------------------------------------------- */
 #define STREAM_DIRECT_LAUNCH 1
 #define STREAM_ZERO_COPY 2
+#define STREAM_SLEEPING_COMPLETION 4
 #define STREAM_RESULT_TAIL 1
 
 typedef struct hrir_server hrir_server;

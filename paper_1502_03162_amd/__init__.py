@@ -56,6 +56,7 @@ assert BLOCK_JOB_DTYPE.itemsize == ctypes.sizeof(BlockJob)
 
 STREAM_DIRECT_LAUNCH = 1
 STREAM_ZERO_COPY = 2
+STREAM_SLEEPING_COMPLETION = 4
 STREAM_RESULT_TAIL = 1
 
 

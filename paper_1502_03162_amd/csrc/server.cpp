@@ -19,7 +19,8 @@
 // STREAM_ZERO_COPY the ring lives in pinned, coherent host memory that the
 // kernel reads and writes in place: a generation is the wait and the launch.
 // A completion thread turns done events into results, handed out by
-// stream_poll.
+// stream_poll; it polls the done event with pauses, or with
+// STREAM_SLEEPING_COMPLETION sleeps in the driver on a blocking-sync event.
 //
 // Admission takes no lock.  Each generation has one 64-bit reservation word
 // (closed bit, epoch, jobs, output samples); a submission claims a job slot
@@ -382,11 +383,16 @@ void completer_main(hrir_server* s) {
         const bool failed = g.failed;
         lk.unlock();
         hipError_t e = hipSuccess;
-        if (!failed)
-            while ((e = hipEventQuery(g.ev_done)) == hipErrorNotReady) {
-                // back off between queries: the loop thread's enqueues share the runtime
-                for (int i = 0; i < 64; ++i) __builtin_ia32_pause();
+        if (!failed) {
+            if (s->flags & STREAM_SLEEPING_COMPLETION) {
+                e = hipEventSynchronize(g.ev_done);    // a blocking-sync event: the thread sleeps
+            } else {
+                while ((e = hipEventQuery(g.ev_done)) == hipErrorNotReady) {
+                    // back off between queries: the loop thread's enqueues share the runtime
+                    for (int i = 0; i < 64; ++i) __builtin_ia32_pause();
+                }
             }
+        }
         const int64_t t_done = now_ns();
         if (e != hipSuccess) {
             set_error(s, "stream loop completion", e);
@@ -440,7 +446,7 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
     *out = nullptr;
     if (max_streams < 1 || max_streams > (1 << 20))
         return fail(HRIR_EINVAL, "stream_open: max_streams=%d outside [1, 2^20]", max_streams);
-    if (flags & ~(STREAM_DIRECT_LAUNCH | STREAM_ZERO_COPY))
+    if (flags & ~(STREAM_DIRECT_LAUNCH | STREAM_ZERO_COPY | STREAM_SLEEPING_COMPLETION))
         return fail(HRIR_EINVAL, "stream_open: unknown flags 0x%x", flags);
     if (hbm_budget < 0) return fail(HRIR_EINVAL, "stream_open: hbm_budget %lld < 0", (long long)hbm_budget);
     int32_t shp[3];
@@ -531,7 +537,10 @@ extern "C" int stream_open(const hrir_plan* plan, int32_t max_streams, int64_t h
             if (e == hipSuccess) e = hipMalloc((void**)&g.d_out, sizeof(float) * 2 * (size_t)cap);
         }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_kernel, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&g.ev_done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&g.ev_done, hipEventDisableTiming | ((flags & STREAM_SLEEPING_COMPLETION)
+                                                                                  ? hipEventBlockingSync
+                                                                                  : 0));
         if (e != hipSuccess) break;
         g.h_jobs = reinterpret_cast<BJob*>(reinterpret_cast<char*>(g.h_hdr) + 64);
         g.d_jobs = reinterpret_cast<BJob*>(reinterpret_cast<char*>(g.d_hdr) + 64);

@@ -155,15 +155,16 @@ def test_mix_matches_oracle_and_alone(dev, flags):
 
 
 def test_launch_forms_agree_bitwise(dev):
-    """Graph or direct launch, device ring or zero-copy host ring: the same
-    bits for every stream."""
+    """Graph or direct launch, device ring or zero-copy host ring, polling
+    or sleeping completion: the same bits for every stream."""
     h = H()
     lf, lg, k, F = 32, 169, 16, 20
     r, p, g = _taps(12, lf, lg, k, F)
     plan = h.Plan(r, p, g, lg)
     scripts = {s: _script(2000 + s, F, n_blocks=5) for s in range(12)}
     outs = []
-    for flags in (0, h.STREAM_DIRECT_LAUNCH, h.STREAM_ZERO_COPY, h.STREAM_ZERO_COPY | h.STREAM_DIRECT_LAUNCH):
+    for flags in (0, h.STREAM_DIRECT_LAUNCH, h.STREAM_ZERO_COPY, h.STREAM_ZERO_COPY | h.STREAM_DIRECT_LAUNCH,
+                  h.STREAM_SLEEPING_COMPLETION, h.STREAM_SLEEPING_COMPLETION | h.STREAM_ZERO_COPY):
         srv = h.Server(plan, max_streams=16, flags=flags)
         outs.append(_drive(srv, scripts, seed=3))
         srv.close()
