@@ -448,7 +448,7 @@ void block_streams_destroy(hrir_streams* streams);
  *                no copy commands, and hbm_budget then bounds the
  *                histories plus that pinned ring; STREAM_SLEEPING_COMPLETION
  *                makes the completion thread wait for each generation in
- *                the driver (a blocking-sync event: the thread sleeps
+ *                the HIP runtime (a blocking-sync event: the thread sleeps
  *                until the GPU signals) instead of polling the event with
  *                pauses, which frees a host core for other servers at the
  *                cost of the wake-up latency.  Starts a loop thread and

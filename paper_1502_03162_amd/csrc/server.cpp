@@ -20,7 +20,7 @@
 // kernel reads and writes in place: a generation is the wait and the launch.
 // A completion thread turns done events into results, handed out by
 // stream_poll; it polls the done event with pauses, or with
-// STREAM_SLEEPING_COMPLETION sleeps in the driver on a blocking-sync event.
+// STREAM_SLEEPING_COMPLETION sleeps in the HIP runtime on a blocking-sync event.
 //
 // Admission takes no lock.  Each generation has one 64-bit reservation word
 // (closed bit, epoch, jobs, output samples); a submission claims a job slot
